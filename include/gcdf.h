@@ -1,0 +1,160 @@
+/*
+ * libgcdf: batched neural GCDF queries on MI355X (gfx950).
+ *
+ * The query is the one a trajectory optimiser makes for every (knot, obstacle
+ * point) pair of the GCDF collision constraints f(p_j, q_i) - delta >= 0
+ * (eq. optimization-in-general, Sec. IV-A of Li et al., "Fast and Safe
+ * Trajectory Optimization for Mobile Manipulators With Neural Configuration
+ * Space Distance Field"):
+ *
+ *   1. express point p_j in the base frame of knot q_i = (x, y, yaw, a1..a6):
+ *      p' = R(yaw)^T (p - (x, y, 0)) (Sec. III-B; Sec. IV-A treats the base
+ *      pose as the origin and biases the obstacle points into that frame);
+ *   2. evaluate the distance network on [p', a1..a6] (Sec. III-C network):
+ *      an MLP 9 -> width x depth -> 1 with SiLU hidden activations;
+ *   3. differentiate it with respect to the full configuration (x, y, yaw,
+ *      a1..a6) by reverse mode through the network and the chain rule through
+ *      the point coordinates (Sec. III-B);
+ *   4. reduce by minimum over the points of each knot.
+ *
+ * Results are knot-major as the constraint vector c_gcdf and its dense
+ * gradient matrix are stacked (eq. cdf_constraints_vector, Sec. IV-B):
+ *   d[i*Np + j]          distance for knot i, point j
+ *   J[(i*Np + j)*9 + c]  d d / d q_i[c], c in (x, y, yaw, a1..a6)
+ *
+ * Memory: every knots/points/output pointer is DEVICE memory owned by the
+ * caller (e.g. a torch tensor).  knots is float32[K][9] (x, y, yaw, a1..a6),
+ * points is float32[Np][3] world coordinates.  The library never frees caller
+ * memory.  Calls are asynchronous on the caller's HIP stream (hipStream_t
+ * passed as void*; NULL = the null stream) and never synchronise the host;
+ * the caller synchronises the stream before reading outputs.
+ *
+ * Errors: every call returns a gcdf_status and never aborts or throws across
+ * the ABI.  The message for the last failed call on the calling thread is
+ * available from gcdf_last_error().  Device faults surface as GCDF_EDEVICE at
+ * the call that observes them.
+ *
+ * Threads: the query calls on one context may be issued by one thread at a
+ * time and on one stream at a time (they share the context's per-knot
+ * workspace); gcdf_submit / gcdf_poll are thread-safe.
+ */
+#ifndef GCDF_H
+#define GCDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GCDF_OK = 0,
+    GCDF_PENDING = 1, /* gcdf_poll: request not finished yet */
+    GCDF_EINVAL = 2,  /* bad argument (message says which) */
+    GCDF_ENOMEM = 3,  /* device allocation failed, or a request can never fit the serving budget */
+    GCDF_EDEVICE = 4, /* HIP runtime error */
+    GCDF_EBUSY = 5    /* serving queue full */
+} gcdf_status;
+
+typedef enum {
+    GCDF_FP32 = 0,   /* all layers in FP32 (matrix cores, FP32 in and out) */
+    GCDF_BF16 = 1,   /* hidden layers on BF16 matrix cores, FP32 accumulate (fast; ~1e-2 error) */
+    GCDF_BF16X2 = 2  /* as BF16 with each activation split into hi + lo BF16 parts (FP32-class error) */
+} gcdf_precision;
+
+typedef struct {
+    int32_t width;          /* hidden width: 256 or 512 */
+    int32_t depth;          /* hidden SiLU layers: 4 */
+    int32_t precision;      /* gcdf_precision */
+    int32_t device;         /* HIP device ordinal; -1 = the calling thread's current device */
+    int64_t max_knots;      /* capacity of the per-knot minimum workspace; 0 = 1<<20 */
+    size_t serve_mem_budget;/* device bytes the serving loop may reserve for requests; 0 = serving off */
+    int32_t serve_slots;    /* max requests in flight in the serving loop; 0 = 64 */
+    int32_t reserved[7];
+} gcdf_config;
+
+typedef struct gcdf_ctx gcdf_ctx;
+
+/* Create a context from a weight blob (host memory, copied; the caller keeps
+ * ownership).  Blob format, little-endian: "GCDF", u32 version = 1,
+ * u32 in_dim = 9, u32 width, u32 depth, 3 reserved u32, then float32 arrays
+ * W1 (width x 9), b1, W2 (width x width), b2, ..., W_depth, b_depth,
+ * w_out (1 x width), b_out, each matrix row-major (out x in) -- the network of
+ * Sec. III-C.  For the BF16 precisions W2..W_depth are rounded to BF16
+ * (round-to-nearest-even); blobs whose hidden matrices already lie on the BF16
+ * grid are multiplied exactly.  Errors: EINVAL (bad config or blob: width not
+ * 256/512, depth != 4, size mismatch), ENOMEM, EDEVICE. */
+gcdf_status gcdf_create(const gcdf_config* cfg, const void* weight_blob, size_t blob_bytes, gcdf_ctx** out);
+
+/* Destroy a context: waits for in-flight serving requests, then frees every
+ * device buffer the library owns.  NULL is ignored. */
+void gcdf_destroy(gcdf_ctx* ctx);
+
+/* Message of the last failed call on the calling thread (library-owned, valid
+ * until the next failing call on that thread).  ctx may be NULL. */
+const char* gcdf_last_error(const gcdf_ctx* ctx);
+
+/* Distance d (float32[K][Np]) for all pairs (steps 1-2).
+ * EINVAL: NULL pointer, K <= 0, Np <= 0, or K*Np*9 overflowing int64. */
+gcdf_status gcdf_eval(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                      float* d, void* stream);
+
+/* Distance d (float32[K][Np]) and configuration gradient J (float32[K][Np][9])
+ * for all pairs (steps 1-3).  Errors as gcdf_eval. */
+gcdf_status gcdf_eval_grad(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                           float* d, float* J, void* stream);
+
+/* Per-knot minimum over points (step 4) without materialising d or J:
+ * dmin (float32[K]) = min_j d[i][j], argmin (int32[K]) = lowest j attaining it,
+ * and, if Jmin != NULL, Jmin (float32[K][9]) = J[i][argmin[i]].  Values are
+ * bitwise equal to the minimum over gcdf_eval_grad's d on the same inputs.
+ * EINVAL also when K > cfg.max_knots or Np > 2^31 - 1. */
+gcdf_status gcdf_knot_min(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                          float* dmin, int32_t* argmin, float* Jmin, void* stream);
+
+/* All four steps in one pass: every non-NULL output among d (float32[K][Np]),
+ * J (float32[K][Np][9]) and dmin/argmin (float32[K], int32[K], given together)
+ * comes from the same fused launch; Jmin (float32[K][9], needs dmin/argmin)
+ * adds a pass over the K argmin pairs.  Results are bitwise equal to those of
+ * gcdf_eval_grad and gcdf_knot_min.  EINVAL if no output is requested, if only
+ * one of dmin/argmin is given, or as gcdf_knot_min for the minimum. */
+gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                       float* d, float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of trajectory-optimisation requests.         */
+/* ------------------------------------------------------------------------ */
+
+/* One request: the pairs of K knots x Np points, with any subset of outputs
+ * (NULL = not wanted; at least one must be given).  All pointers are device
+ * memory owned by the caller and must stay valid until gcdf_poll returns
+ * GCDF_OK (or an error) for the request's ticket. */
+typedef struct {
+    const float* knots;
+    int64_t K;
+    const float* points;
+    int64_t Np;
+    float* d;        /* float32[K][Np] */
+    float* J;        /* float32[K][Np][9] */
+    float* dmin;     /* float32[K] */
+    int32_t* argmin; /* int32[K]  (given together with dmin) */
+} gcdf_request;
+
+/* Queue a request and return at once with its ticket.  The serving loop
+ * admits queued requests while in-flight slots and the memory budget allow,
+ * and runs all admitted requests' tiles in shared persistent launches.
+ * ENOMEM: the request alone exceeds serve_mem_budget.  EBUSY: too many queued.
+ * EINVAL: bad request or serving disabled (serve_mem_budget == 0). */
+gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket);
+
+/* GCDF_OK when the ticket's outputs are complete and visible to the caller's
+ * later stream work, GCDF_PENDING while not, EINVAL for an unknown ticket
+ * (including one already reported complete), EDEVICE on a device error. */
+gcdf_status gcdf_poll(gcdf_ctx* ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCDF_H */

@@ -1,0 +1,290 @@
+// C-ABI of libgcdf: contexts, argument checking, weight packing and launches.
+// The query semantics are documented in include/gcdf.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gcdf.h"
+#include "gcdf_internal.h"
+#include "gcdf_serve.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gcdf_status fail(gcdf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+gcdf_status hip_fail(hipError_t e, const char* what) {
+  return fail(GCDF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kHeader = 32;
+
+}  // namespace
+
+struct gcdf_ctx {
+  gcdf_config cfg{};
+  int device = 0;
+  int num_cu = 0;
+  gcdf::DevNet net{};
+  void* wbuf = nullptr;               // all packed weights
+  unsigned long long* minkey = nullptr;  // [max_knots]
+  int64_t* pair_k = nullptr;          // [max_knots]
+  int64_t* pair_p = nullptr;          // [max_knots]
+  gcdf::Server* server = nullptr;
+};
+
+namespace {
+
+// RAII: make `dev` current for the scope of a call, restoring the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+gcdf_status check_query(const gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!knots || !points) return fail(GCDF_EINVAL, "knots/points pointer is NULL");
+  if (K <= 0 || Np <= 0) return fail(GCDF_EINVAL, "K and Np must be positive (K=%lld, Np=%lld)", (long long)K, (long long)Np);
+  if (K > INT64_MAX / 9 / Np) return fail(GCDF_EINVAL, "K*Np*9 overflows int64");
+  return GCDF_OK;
+}
+
+}  // namespace
+
+namespace gcdf {
+
+// Enqueue a dense query on `s` (used by the eval calls and the serving loop).
+hipError_t enqueue_dense(const gcdf_ctx* ctx, const Job& job, bool want_grad, hipStream_t s) {
+  return launch_fused(ctx->net, job, false, want_grad, ctx->num_cu, s);
+}
+
+const DevNet& ctx_net(const gcdf_ctx* ctx) { return ctx->net; }
+int ctx_num_cu(const gcdf_ctx* ctx) { return ctx->num_cu; }
+int ctx_device(const gcdf_ctx* ctx) { return ctx->device; }
+
+}  // namespace gcdf
+
+extern "C" {
+
+const char* gcdf_last_error(const gcdf_ctx*) { return g_err.c_str(); }
+
+gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, gcdf_ctx** out) {
+  if (!cfg || !blob || !out) return fail(GCDF_EINVAL, "NULL argument to gcdf_create");
+  *out = nullptr;
+  if (cfg->width != 256 && cfg->width != 512) return fail(GCDF_EINVAL, "width must be 256 or 512 (got %d)", cfg->width);
+  if (cfg->depth != 4) return fail(GCDF_EINVAL, "depth must be 4 (got %d)", cfg->depth);
+  if (cfg->precision < GCDF_FP32 || cfg->precision > GCDF_BF16X2)
+    return fail(GCDF_EINVAL, "unknown precision %d", cfg->precision);
+  if (cfg->max_knots < 0) return fail(GCDF_EINVAL, "max_knots must be >= 0");
+  const int W = cfg->width;
+  // blob: header + W1, b1, (W2, b2) .. (W4, b4), w_out, b_out
+  const size_t nfloat = (size_t)W * 9 + W + 3 * ((size_t)W * W + W) + W + 1;
+  if (bytes != kHeader + 4 * nfloat) return fail(GCDF_EINVAL, "weight blob is %zu bytes, expected %zu", bytes, kHeader + 4 * nfloat);
+  const uint32_t* hdr = static_cast<const uint32_t*>(blob);
+  if (std::memcmp(blob, "GCDF", 4) != 0 || hdr[1] != 1 || hdr[2] != 9 || (int)hdr[3] != W || (int)hdr[4] != 4)
+    return fail(GCDF_EINVAL, "weight blob header does not match (magic/version/in_dim/width/depth)");
+
+  int dev = cfg->device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(GCDF_EDEVICE, "no current HIP device");
+  DeviceGuard guard(dev);
+  if (!guard.ok) return fail(GCDF_EDEVICE, "hipSetDevice(%d) failed", dev);
+
+  gcdf_ctx* c = new gcdf_ctx;
+  c->cfg = *cfg;
+  if (c->cfg.max_knots == 0) c->cfg.max_knots = 1 << 20;
+  c->device = dev;
+  hipError_t e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  const int mode = cfg->precision;
+  const size_t mbytes = gcdf::packed_matrix_bytes(W, mode);
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t off_w1 = 0;
+  const size_t off_bh = align(off_w1 + (size_t)W * 12 * 4);
+  const size_t off_w5 = align(off_bh + (size_t)3 * W * 4);
+  const size_t off_m = align(off_w5 + (size_t)W * 4);
+  const size_t total = off_m + 6 * align(mbytes);
+  const size_t ws = (size_t)c->cfg.max_knots * (8 + 8 + 8);
+  float* staging = nullptr;
+  e = hipMalloc(&c->wbuf, total);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->minkey), ws);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&staging), 4 * nfloat);
+  if (e != hipSuccess) {
+    hipFree(staging);
+    gcdf_destroy(c);
+    return fail(GCDF_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  c->pair_k = reinterpret_cast<int64_t*>(c->minkey + c->cfg.max_knots);
+  c->pair_p = c->pair_k + c->cfg.max_knots;
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMemcpyAsync(staging, static_cast<const char*>(blob) + kHeader, 4 * nfloat, hipMemcpyHostToDevice, s);
+  char* base = static_cast<char*>(c->wbuf);
+  // offsets of the source arrays inside staging (floats)
+  const float* W1 = staging;
+  const float* b1 = W1 + (size_t)W * 9;
+  const float* Wl[3];
+  const float* bl[3];
+  {
+    const float* p = b1 + W;
+    for (int l = 0; l < 3; ++l) {
+      Wl[l] = p;
+      bl[l] = p + (size_t)W * W;
+      p = bl[l] + W;
+    }
+    c->net.b5 = 0.f;
+    std::memcpy(&c->net.b5, static_cast<const char*>(blob) + kHeader + 4 * (nfloat - 1), 4);
+  }
+  const float* w5src = bl[2] + W;
+  float* w1p = reinterpret_cast<float*>(base + off_w1);
+  float* bh = reinterpret_cast<float*>(base + off_bh);
+  float* w5 = reinterpret_cast<float*>(base + off_w5);
+  // biases b2..b4 are not contiguous in the blob: reorder them one by one
+  if (e == hipSuccess) e = gcdf::pack_input_layer(W1, b1, w1p, W, s);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = gcdf::pack_row_vectors(bl[l], bh + (size_t)l * W, W, 1, s);
+  if (e == hipSuccess) e = gcdf::pack_row_vectors(w5src, w5, W, 1, s);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    void* f = base + off_m + (size_t)l * align(mbytes);
+    void* b = base + off_m + (size_t)(3 + l) * align(mbytes);
+    e = gcdf::pack_matrix(Wl[l], f, W, mode, false, s);
+    if (e == hipSuccess) e = gcdf::pack_matrix(Wl[l], b, W, mode, true, s);
+    c->net.fwd[l] = f;
+    c->net.bwd[l] = b;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (s) hipStreamDestroy(s);
+  hipFree(staging);
+  if (e != hipSuccess) {
+    gcdf_destroy(c);
+    return hip_fail(e, "weight packing");
+  }
+  c->net.width = W;
+  c->net.mode = mode;
+  c->net.w1p = w1p;
+  c->net.bh = bh;
+  c->net.w5 = w5;
+  if (cfg->serve_mem_budget > 0) {
+    gcdf_status st = gcdf::server_start(c, cfg->serve_mem_budget, cfg->serve_slots > 0 ? cfg->serve_slots : 64, &c->server);
+    if (st != GCDF_OK) {
+      std::string msg = g_err;
+      gcdf_destroy(c);
+      g_err = msg;
+      return st;
+    }
+  }
+  *out = c;
+  return GCDF_OK;
+}
+
+void gcdf_destroy(gcdf_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard guard(ctx->device);
+  if (ctx->server) gcdf::server_stop(ctx->server);
+  hipFree(ctx->wbuf);
+  hipFree(ctx->minkey);
+  delete ctx;
+}
+
+gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
+                       float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream) {
+  gcdf_status st = check_query(ctx, knots, K, points, Np);
+  if (st != GCDF_OK) return st;
+  const bool want_min = dmin || argmin;
+  if (!d && !J && !want_min) return fail(GCDF_EINVAL, "no output requested");
+  if (want_min && !(dmin && argmin)) return fail(GCDF_EINVAL, "dmin and argmin must be given together");
+  if (Jmin && !want_min) return fail(GCDF_EINVAL, "Jmin needs dmin and argmin");
+  if (want_min && K > ctx->cfg.max_knots)
+    return fail(GCDF_EINVAL, "K=%lld exceeds max_knots=%lld", (long long)K, (long long)ctx->cfg.max_knots);
+  if (want_min && Np > INT32_MAX) return fail(GCDF_EINVAL, "Np=%lld exceeds 2^31-1", (long long)Np);
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (want_min) e = gcdf::launch_minkey_init(ctx->minkey, K, s);
+  gcdf::Job job{};
+  job.knots = knots;
+  job.points = points;
+  job.K = K;
+  job.Np = Np;
+  job.d = d;
+  job.J = J;
+  job.minkey = want_min ? ctx->minkey : nullptr;
+  if (e == hipSuccess) e = gcdf::launch_fused(ctx->net, job, false, J != nullptr, ctx->num_cu, s);
+  if (e == hipSuccess && want_min)
+    e = gcdf::launch_minkey_decode(ctx->minkey, K, dmin, argmin, Jmin ? ctx->pair_k : nullptr,
+                                   Jmin ? ctx->pair_p : nullptr, s);
+  if (e == hipSuccess && Jmin) {
+    gcdf::Job pj{};
+    pj.knots = knots;
+    pj.points = points;
+    pj.K = K;
+    pj.Np = Np;
+    pj.kidx = ctx->pair_k;
+    pj.pidx = ctx->pair_p;
+    pj.npairs = K;
+    pj.J = Jmin;
+    e = gcdf::launch_fused(ctx->net, pj, true, true, ctx->num_cu, s);
+  }
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_query launch");
+}
+
+gcdf_status gcdf_eval(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
+                      void* stream) {
+  if (!d) return fail(GCDF_EINVAL, "d is NULL");
+  return gcdf_query(ctx, knots, K, points, Np, d, nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+gcdf_status gcdf_eval_grad(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
+                           float* J, void* stream) {
+  if (!d || !J) return fail(GCDF_EINVAL, "d or J is NULL");
+  return gcdf_query(ctx, knots, K, points, Np, d, J, nullptr, nullptr, nullptr, stream);
+}
+
+gcdf_status gcdf_knot_min(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* dmin,
+                          int32_t* argmin, float* Jmin, void* stream) {
+  if (!dmin || !argmin) return fail(GCDF_EINVAL, "dmin or argmin is NULL");
+  return gcdf_query(ctx, knots, K, points, Np, nullptr, nullptr, dmin, argmin, Jmin, stream);
+}
+
+gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket) {
+  if (!ctx || !req || !ticket) return fail(GCDF_EINVAL, "NULL argument to gcdf_submit");
+  if (!ctx->server) return fail(GCDF_EINVAL, "serving is disabled (serve_mem_budget == 0)");
+  return gcdf::server_submit(ctx->server, req, ticket);
+}
+
+gcdf_status gcdf_poll(gcdf_ctx* ctx, uint64_t ticket) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!ctx->server) return fail(GCDF_EINVAL, "serving is disabled (serve_mem_budget == 0)");
+  return gcdf::server_poll(ctx->server, ticket);
+}
+
+}  // extern "C"
+
+namespace gcdf {
+gcdf_status set_error(gcdf_status st, const char* msg) {
+  g_err = msg;
+  return st;
+}
+}  // namespace gcdf

@@ -1,0 +1,761 @@
+// Fused batched neural-GCDF query kernel for gfx950 (MI355X).
+//
+// One workgroup (4 waves, one per SIMD) owns a tile of 64 queries: 64 points
+// of one knot (dense all-pairs mode) or 64 entries of a pair list.  For the
+// tile it runs the whole query without touching HBM in between:
+//   base-frame transform -> input layer (FP32, VALU) -> hidden layers on
+//   matrix cores -> output dot -> reverse sweep on matrix cores (transposed
+//   weights) -> input-layer gradient (FP32) -> chain rule to (x, y, yaw, arm)
+//   -> stores of d / J -> per-knot minimum (64-bit ordered-key atomic min).
+// (Steps of the query: Sec. III-B base-frame transform and chain rule,
+// Sec. III-C network on [p', a], Sec. IV-A constraint over all knot/point
+// pairs, Sec. IV-B knot-major stacking.)
+//
+// Work split inside the tile: every hidden layer is C[W x 64] = M[W x W] B[W x 64]
+// with M = W_l (forward) or W_l^T (reverse) and B = the previous layer's
+// activations (forward) or back-propagated gradients (reverse).  Wave w owns
+// output rows [w*W/4, (w+1)*W/4) for all 64 queries; B lives in LDS (written by
+// the epilogue of the previous layer, read by all four waves); the A fragments
+// stream from global memory (L2-resident, pre-packed so each 32x16 fragment is
+// one contiguous 1 KiB block: one dwordx4 per lane).  Each weight byte fetched
+// is used for 64 queries.
+//
+// Precision modes:
+//   FP32   : v_mfma_f32_32x32x2_f32, activations FP32 in LDS.
+//   BF16   : v_mfma_f32_32x32x16_bf16, activations rounded to BF16, FP32 accumulate.
+//   BF16X2 : as BF16 but each activation is split x = hi + lo (both BF16) and both
+//            halves are multiplied (2 MFMAs per fragment pair); hidden weights must
+//            lie on the BF16 grid to be exact.
+// The SiLU derivative needed by the reverse sweep is kept in FP32 registers for
+// layers 2 and 3 and recomputed for layer 1 from the input layer.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "gcdf_internal.h"
+
+namespace gcdf {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// SiLU and its derivative from one exp and one reciprocal.
+__device__ __forceinline__ void silu_fwd(float z, float& h, float& dh) {
+  float t = __builtin_amdgcn_exp2f(-z * kLog2e);
+  float sg = __builtin_amdgcn_rcpf(1.0f + t);
+  h = z * sg;
+  dh = sg + h * (1.0f - sg);  // s (1 + z (1 - s))
+}
+__device__ __forceinline__ float silu_only(float z) {
+  float t = __builtin_amdgcn_exp2f(-z * kLog2e);
+  return z * __builtin_amdgcn_rcpf(1.0f + t);
+}
+__device__ __forceinline__ float silu_prime_only(float z) {
+  float t = __builtin_amdgcn_exp2f(-z * kLog2e);
+  float sg = __builtin_amdgcn_rcpf(1.0f + t);
+  return sg + z * sg * (1.0f - sg);
+}
+
+// The reverse sweep's SiLU' values are parked in accumulation registers
+// (AGPRs), which the matrix cores do not need because accumulators are kept in
+// ordinary VGPRs; vector ALU instructions cannot read AGPRs, so values move with
+// v_accvgpr_write / v_accvgpr_read.
+__device__ __forceinline__ float park(float x) {
+  float a;
+  asm("v_accvgpr_write_b32 %0, %1" : "=a"(a) : "v"(x));
+  return a;
+}
+// `after` is an extra input that orders the read after the value it is used
+// with (the layer's finished accumulator); otherwise the compiler hoists the
+// read above the K loop and keeps every unparked value live through it.
+__device__ __forceinline__ float unpark(float a, float after) {
+  float x;
+  asm("v_accvgpr_read_b32 %0, %1 ; %2" : "=v"(x) : "a"(a), "v"(after));
+  return x;
+}
+
+// Input-layer pre-activation, in one fixed order shared by every path:
+// c = b1 + sum_a W1[r][3+a] arm[a] (the knot's arm term), then
+// z1 = c + W1[r][0] p'x + W1[r][1] p'y + W1[r][2] p'z.
+__device__ __forceinline__ float arm_term(float b1, float w3, float w4, float w5, float w6, float w7, float w8,
+                                          const float* arm) {
+  float c = b1;
+  c += w3 * arm[0];
+  c += w4 * arm[1];
+  c += w5 * arm[2];
+  c += w6 * arm[3];
+  c += w7 * arm[4];
+  c += w8 * arm[5];
+  return c;
+}
+__device__ __forceinline__ float input_preact(float c, float w0, float w1, float w2, const float* x) {
+  return c + w0 * x[0] + w1 * x[1] + w2 * x[2];
+}
+
+template <int W>
+struct Geo {
+  static constexpr int MT = W / (32 * kWaves);       // 32-row M tiles per wave
+  static constexpr int NKB = W / 16;                 // 16-deep K blocks (bf16)
+  static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
+  static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
+  static constexpr int XIN_FLOATS = 16;              // per query: p'(3), cos, sin, arm(6), pad
+  static constexpr int RED_VALS = 10;                // d + 9 input-gradient components
+  static constexpr int LDS_BYTES =
+      ACT_BYTES + kTileQ * XIN_FLOATS * 4 + W * 4 + kWaves * RED_VALS * kTileQ * 4 + 4 * W * 4;
+};
+
+// ----------------------------------------------------------------------------
+// Activation tile in LDS (64 query columns).
+//  bf16 modes: hi plane then lo plane, element (k, n) at ((k/16)*64 + n)*16 + k%16.
+//  fp32 mode : element (k, n) at (((k/8)*64 + n)*2 + k%2)*4 + (k%8)/2.
+// Both put the 8 (bf16) or 4 (fp32) K-consecutive values one MFMA lane needs in
+// 16 contiguous bytes, and in both the B fragment of K step s and column block
+// nt starts at byte s*2048 + nt*1024, lane (n0, kh) at +n0*32 + kh*16.
+//
+// Every address below is a per-lane base (computed once) plus a compile-time
+// constant, so the constants fold into the instructions' offset fields instead
+// of occupying registers.
+// ----------------------------------------------------------------------------
+template <int W, int MODE>
+struct Lane {
+  static constexpr int MT = W / (32 * kWaves);
+  int lane, wave, h, n0, kh, rbase;
+  char* act_w;        // write base, hi plane (or the fp32 tile)
+  char* act_w_lo;     // write base, lo plane
+  const char* act_r;  // read base
+  __device__ __forceinline__ Lane(char* act, int tid) {
+    lane = tid & 63;
+    wave = tid >> 6;
+    h = lane >> 5;
+    kh = h;
+    n0 = lane & 31;
+    rbase = 32 * MT * wave;
+    if constexpr (MODE == kFP32) {
+      act_w = act + 4 * (((rbase >> 3) * kTileQ + n0) * 8 + 2 * h);
+    } else {
+      act_w = act + 2 * (((rbase >> 4) * kTileQ + n0) * 16 + 4 * h);
+    }
+    act_w_lo = act_w + W * kTileQ * 2;
+    act_r = act + n0 * 32 + kh * 16;
+  }
+};
+
+// Write rows R0..R0+3 (R0 = rbase + 32 i + 8 g + 4 h) of column n = 32 nt + n0.
+template <int W, int MODE, int I, int G, int NT>
+__device__ __forceinline__ void act_store4(const Lane<W, MODE>& L, const float v[4]) {
+  if constexpr (MODE == kFP32) {
+    constexpr int off = (4 * I + G) * 2048 + NT * 1024;
+    *reinterpret_cast<f32x2*>(L.act_w + off) = f32x2{v[0], v[2]};       // rows R0, R0+2 (k%2 = 0)
+    *reinterpret_cast<f32x2*>(L.act_w + off + 16) = f32x2{v[1], v[3]};  // rows R0+1, R0+3 (k%2 = 1)
+  } else {
+    constexpr int off = (2 * I + (G >> 1)) * 2048 + NT * 1024 + 16 * (G & 1);
+    bf16x4 h4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h4[r] = (__bf16)v[r];
+    *reinterpret_cast<bf16x4*>(L.act_w + off) = h4;
+    if constexpr (MODE == kBF16X2) {
+      bf16x4 l4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) l4[r] = (__bf16)(v[r] - (float)h4[r]);
+      *reinterpret_cast<bf16x4*>(L.act_w_lo + off) = l4;
+    }
+  }
+}
+
+// Compile-time loop helper: f(integral_constant<0>), ..., f(integral_constant<N-1>).
+template <int N, int B = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < N) {
+    f(std::integral_constant<int, B>{});
+    static_for<N, B + 1>(f);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// acc[i][nt] += M[rows of wave, :] x act[:, 32nt .. 32nt+31]
+// A fragments: this wave's stream, chunk (kstep, i) at ((kstep*MT + i)*64 + lane)*16 bytes.
+// The K loop is unrolled by two with two static fragment buffers: the loads for
+// step s+1 are in flight while the matrix cores work on step s.
+// ----------------------------------------------------------------------------
+template <int W, int MODE>
+__device__ __forceinline__ void gemm_step(f32x16 (&acc)[Geo<W>::MT][2], const f32x4 (&af)[Geo<W>::MT],
+                                          const char* br) {
+  constexpr int MT = Geo<W>::MT;
+  if constexpr (MODE == kFP32) {
+    f32x4 bf[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) bf[nt] = *reinterpret_cast<const f32x4*>(br + nt * 1024);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], bf[nt][q], acc[i][nt], 0, 0, 0);
+  } else {
+    bf16x8 bh[2], bl[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      bh[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 1024);
+      if constexpr (MODE == kBF16X2) bl[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 1024);
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, bh[nt], acc[i][nt], 0, 0, 0);
+    }
+    if constexpr (MODE == kBF16X2) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, bl[nt], acc[i][nt], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void load_frags(f32x4 (&af)[Geo<W>::MT], const char* __restrict__ a) {
+#pragma unroll
+  for (int i = 0; i < Geo<W>::MT; ++i) af[i] = *reinterpret_cast<const f32x4*>(a + i * 1024);
+}
+
+// A: this lane's position in the wave's fragment stream (stream base + lane*16).
+template <int W, int MODE>
+__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[Geo<W>::MT][2], const char* __restrict__ A,
+                                           const char* br) {
+  constexpr int MT = Geo<W>::MT;
+  constexpr int NS = (MODE == kFP32) ? Geo<W>::NK8 : Geo<W>::NKB;  // even
+  f32x4 a0[MT], a1[MT];
+  load_frags<W>(a0, A);
+#pragma unroll 1
+  for (int s = 0; s < NS; s += 2) {
+    load_frags<W>(a1, A + MT * 1024);
+    gemm_step<W, MODE>(acc, a0, br);
+    const char* an = (s + 2 < NS) ? A + 2 * MT * 1024 : A + MT * 1024;
+    load_frags<W>(a0, an);
+    gemm_step<W, MODE>(acc, a1, br + 2048);
+    A += 2 * MT * 1024;
+    br += 4096;
+  }
+}
+
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ----------------------------------------------------------------------------
+// Layer bodies (compile-time layer index so every register array is static).
+// Element j of acc[i][nt] is row R = rbase + 32 i + 8 (j/4) + 4 (lane/32) + j%4
+// of the layer output and query column n = 32 nt + lane%32.
+// ----------------------------------------------------------------------------
+// Row-indexed vectors (b1..b4, w_out, the input-layer rows and the per-knot
+// arm term) are stored in lane-major order: the 16*MT rows one lane touches,
+// R = rbase + 32 i + 8 g + 4 h + r, sit at position
+// ((wave*2 + h)*MT + i)*16 + 4 g + r, so each lane addresses them from one base
+// with small constant offsets.
+template <int W, int MODE>
+struct Bases {
+  const float* bh;    // LDS copy of b2, b3, b4 (lane-major), at this lane's block
+  const float* w5;    // LDS copy of w_out (lane-major), at this lane's block
+  const float* w1;    // input layer rows (lane-major, 12 floats per row), at this lane's block
+  const float* crow;  // per-knot input-layer constant (LDS, lane-major), at this lane's block
+  const float* xin;   // xin + n0 * XIN_FLOATS
+  const char* A;      // lane offset inside a wave's fragment stream: wave*stream_bytes + lane*16
+};
+
+template <int W, int MODE, int L>
+__device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
+                                           float (&sp)[2][Geo<W>::MT][2][16], float (&dpart)[2], int want_grad) {
+  constexpr int MT = Geo<W>::MT;
+  f32x16 acc[MT][2];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 b4 = *reinterpret_cast<const f32x4*>(b.bh + L * W + 16 * i + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][nt][4 * g + r] = b4[r];
+    }
+  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.fwd[L]) + (size_t)b.A, ln.act_r);
+  __syncthreads();
+  static_for<MT>([&](auto I) {
+    static_for<4>([&](auto G) {
+      f32x4 w5r = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (L == 2) w5r = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 4 * G);
+      static_for<2>([&](auto NT) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float hv, dv;
+          silu_fwd(acc[I][NT][4 * G + r], hv, dv);
+          if constexpr (L < 2) {
+            sp[L][I][NT][4 * G + r] = park(dv);
+            v[r] = hv;
+          } else {
+            dpart[NT] += w5r[r] * hv;
+            v[r] = w5r[r] * dv;  // g4 = w5 * SiLU'(z4)
+          }
+        }
+        if (L < 2 || want_grad) act_store4<W, MODE, I, G, NT>(ln, v);
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  });
+  if constexpr (L == 2) {
+    // Materialise the output-layer partial sums here; left alone, the compiler
+    // sinks them to their use after the reverse sweep and keeps every h4 and
+    // w_out value live through it.
+    asm volatile("" : "+v"(dpart[0]), "+v"(dpart[1]));
+  }
+  __syncthreads();
+}
+
+template <int W, int MODE, int L>
+__device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
+                                           const float (&sp)[2][Geo<W>::MT][2][16]) {
+  constexpr int MT = Geo<W>::MT;
+  f32x16 acc[MT][2];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
+  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.bwd[L]) + (size_t)b.A, ln.act_r);
+  __syncthreads();
+  static_for<MT>([&](auto I) {
+    static_for<4>([&](auto G) {
+      static_for<2>([&](auto NT) {
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = acc[I][NT][4 * G + r] * unpark(sp[L - 1][I][NT][4 * G + r], acc[I][NT][4 * G + r]);
+        act_store4<W, MODE, I, G, NT>(ln, v);
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  });
+  __syncthreads();
+}
+
+// Last reverse layer: g1 = (W2^T g2) * SiLU'(z1) with z1 recomputed, then the
+// input-layer gradient e = W1^T g1 accumulated per lane in FP32.
+template <int W, int MODE, bool PAIRS>
+__device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
+                                          float (&epart)[2][9]) {
+  constexpr int MT = Geo<W>::MT;
+  constexpr int XF = Geo<W>::XIN_FLOATS;
+  f32x16 acc[MT][2];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
+  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.bwd[0]) + (size_t)b.A, ln.act_r);
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float* w = b.w1 + (16 * i + 4 * g + r) * 12;
+        const f32x4 wa = *reinterpret_cast<const f32x4*>(w);
+        const f32x4 wb = *reinterpret_cast<const f32x4*>(w + 4);
+        const f32x2 wc = *reinterpret_cast<const f32x2*>(w + 8);
+        const float cr = PAIRS ? wa[3] : b.crow[16 * i + 4 * g + r];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const float* x = b.xin + nt * 32 * XF;
+          const float c = PAIRS ? arm_term(wa[3], wb[0], wb[1], wb[2], wb[3], wc[0], wc[1], x + 5) : cr;
+          const float z = input_preact(c, wa[0], wa[1], wa[2], x);
+          const float g1 = acc[i][nt][4 * g + r] * silu_prime_only(z);
+          epart[nt][0] += wa[0] * g1;
+          epart[nt][1] += wa[1] * g1;
+          epart[nt][2] += wa[2] * g1;
+          epart[nt][3] += wb[0] * g1;
+          epart[nt][4] += wb[1] * g1;
+          epart[nt][5] += wb[2] * g1;
+          epart[nt][6] += wb[3] * g1;
+          epart[nt][7] += wc[0] * g1;
+          epart[nt][8] += wc[1] * g1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+}
+
+// Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.
+template <int W, int MODE, bool PAIRS>
+__device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b) {
+  constexpr int MT = Geo<W>::MT;
+  constexpr int XF = Geo<W>::XIN_FLOATS;
+  static_for<MT>([&](auto I) {
+    static_for<4>([&](auto G) {
+      f32x4 wa[4], wb[4];
+      f32x2 wc[4];
+      float cr[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float* w = b.w1 + (16 * I + 4 * G + r) * 12;
+        wa[r] = *reinterpret_cast<const f32x4*>(w);
+        if constexpr (PAIRS) {
+          wb[r] = *reinterpret_cast<const f32x4*>(w + 4);
+          wc[r] = *reinterpret_cast<const f32x2*>(w + 8);
+          cr[r] = wa[r][3];
+        } else {
+          cr[r] = b.crow[16 * I + 4 * G + r];
+        }
+      }
+      static_for<2>([&](auto NT) {
+        const float* x = b.xin + NT * 32 * XF;
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float c = cr[r];
+          if constexpr (PAIRS) c = arm_term(wa[r][3], wb[r][0], wb[r][1], wb[r][2], wb[r][3], wc[r][0], wc[r][1], x + 5);
+          v[r] = silu_only(input_preact(c, wa[r][0], wa[r][1], wa[r][2], x));
+        }
+        act_store4<W, MODE, I, G, NT>(ln, v);
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  });
+}
+
+// ----------------------------------------------------------------------------
+// The fused kernel.
+// ----------------------------------------------------------------------------
+template <int W, int MODE, bool PAIRS, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, const Job job, int want_grad,
+                                                             int64_t ntiles) {
+  using G = Geo<W>;
+  constexpr int MT = G::MT;
+  constexpr int XF = G::XIN_FLOATS;
+  __shared__ __attribute__((aligned(16))) char lds[G::LDS_BYTES];
+  char* act = lds;
+  float* xin = reinterpret_cast<float*>(lds + G::ACT_BYTES);               // [64][16]
+  float* crow = xin + kTileQ * XF;                                         // [W]
+  float* red = crow + W;                                                   // [4][10][64]
+  float* vec = red + kWaves * G::RED_VALS * kTileQ;                        // [4][W]: b2, b3, b4, w_out
+
+  const int tid = threadIdx.x;
+  const Lane<W, MODE> ln(act, tid);
+  for (int i = tid; i < 4 * W; i += kThreads) vec[i] = i < 3 * W ? net.bh[i] : net.w5[i - 3 * W];
+  // bytes of one matrix's fragment stream per wave (1 KiB per fragment)
+  const size_t stream_bytes = (size_t)(MODE == kFP32 ? G::NK8 : G::NKB) * MT * 1024;
+  Bases<W, MODE> b;
+  const int lblk = (ln.wave * 2 + ln.h) * MT * 16;  // this lane's block of lane-major rows
+  b.bh = vec + lblk;
+  b.w5 = vec + 3 * W + lblk;
+  b.w1 = net.w1p + lblk * 12;
+  b.crow = crow + lblk;
+  b.xin = xin + ln.n0 * XF;
+  b.A = reinterpret_cast<const char*>((size_t)ln.wave * stream_bytes + (size_t)ln.lane * 16);
+
+  const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
+  const int64_t qlimit = PAIRS ? job.npairs : job.Np;
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t kk = 0, q0 = 0;
+    if constexpr (PAIRS) {
+      q0 = tile * kTileQ;
+    } else {
+      kk = tile / nblk;
+      q0 = (tile - kk * nblk) * kTileQ;
+    }
+
+    // ---- prologue: base-frame points (+ per-knot arm term of the input layer) ----
+    if (tid < kTileQ) {
+      const int64_t q = q0 + tid;
+      const int64_t qc = q < qlimit ? q : qlimit - 1;   // clamp the ragged tail (never stored)
+      int64_t ki, pi;
+      if constexpr (PAIRS) {
+        ki = job.kidx ? job.kidx[qc] : qc;
+        pi = job.pidx ? job.pidx[qc] : qc;
+      } else {
+        ki = kk;
+        pi = qc;
+      }
+      const float* kn = job.knots + ki * kInDim;
+      const float* pt = job.points + pi * 3;
+      float sn, cs;
+      sincosf(kn[2], &sn, &cs);
+      const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
+      float* x = xin + tid * XF;
+      x[0] = cs * ux + sn * uy;
+      x[1] = -sn * ux + cs * uy;
+      x[2] = pt[2];
+      x[3] = cs;
+      x[4] = sn;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
+    }
+    if constexpr (!PAIRS) {
+      const float* kn = job.knots + kk * kInDim;
+      for (int r = tid; r < W; r += kThreads) {  // r: lane-major position
+        const float* w = net.w1p + r * 12;
+        crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], kn + 3);
+      }
+    }
+    __syncthreads();
+
+    fwd_input<W, MODE, PAIRS>(ln, b);
+    __syncthreads();
+
+    // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
+    float sp[2][MT][2][16];
+    float dpart[2] = {0.f, 0.f};
+    fwd_hidden<W, MODE, 0>(net, ln, b, sp, dpart, want_grad);
+    fwd_hidden<W, MODE, 1>(net, ln, b, sp, dpart, want_grad);
+    fwd_hidden<W, MODE, 2>(net, ln, b, sp, dpart, want_grad);
+
+    // ---- reverse sweep: W4^T, W3^T (into LDS), W2^T (into the input-layer gradient) ----
+    float epart[2][9];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) epart[nt][c] = 0.f;
+    if (want_grad) {
+      bwd_hidden<W, MODE, 2>(net, ln, b, sp);
+      bwd_hidden<W, MODE, 1>(net, ln, b, sp);
+      bwd_input<W, MODE, PAIRS>(net, ln, b, epart);
+    }
+
+    // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      dpart[nt] += __shfl_xor(dpart[nt], 32);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
+    }
+    if (ln.h == 0) {
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const int n = 32 * nt + ln.n0;
+        red[(ln.wave * G::RED_VALS + 0) * kTileQ + n] = dpart[nt];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) red[(ln.wave * G::RED_VALS + 1 + c) * kTileQ + n] = epart[nt][c];
+      }
+    }
+    __syncthreads();
+
+    // ---- per query: final sums, chain rule, stores, per-knot minimum ----
+    if (tid < kTileQ) {
+      const int n = tid;
+      float vals[G::RED_VALS];
+#pragma unroll
+      for (int c = 0; c < G::RED_VALS; ++c) {
+        float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
+        vals[c] = sum;
+      }
+      const float dv = vals[0] + net.b5;
+      const int64_t q = q0 + n;
+      const bool valid = q < qlimit;
+      const int64_t out = PAIRS ? q : kk * job.Np + q;
+      if (valid && job.d) job.d[out] = dv;
+      if (valid && job.J && want_grad) {
+        const float* x = xin + n * XF;
+        const float cs = x[3], sn = x[4];
+        const float* e = vals + 1;
+        float* Jo = job.J + out * kInDim;
+        Jo[0] = -(cs * e[0] - sn * e[1]);
+        Jo[1] = -(sn * e[0] + cs * e[1]);
+        Jo[2] = e[0] * x[1] - e[1] * x[0];
+#pragma unroll
+        for (int c = 3; c < 9; ++c) Jo[c] = e[c];
+      }
+      if constexpr (!PAIRS) {
+        if (job.minkey) {
+          unsigned long long key = valid ? (((unsigned long long)ordered_bits(dv) << 32) | (uint32_t)q) : ~0ull;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            unsigned long long o = __shfl_xor(key, off);
+            key = o < key ? o : key;
+          }
+          if (n == 0 && key != ~0ull) atomicMin(job.minkey + kk, key);
+        }
+      }
+    }
+    // The next tile's prologue rewrites xin and crow: every wave has passed the
+    // barrier above (crow's last reader), and xin's readers here are wave 0,
+    // which also writes it, in program order.
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Packing and helper kernels
+// ----------------------------------------------------------------------------
+size_t packed_matrix_bytes(int width, int mode) {
+  return (size_t)width * width * (mode == kFP32 ? 4 : 2);
+}
+
+// Output element -> source element.  Chunk order: [wave][kstep][i] with 64 lanes per chunk.
+__global__ void pack_bf16_kernel(const float* __restrict__ src, __bf16* __restrict__ dst, int W, int transpose) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W * W) return;
+  const int MT = W / (32 * kWaves), NKB = W / 16;
+  const int e = idx & 7;
+  const int lane = (idx >> 3) & 63;
+  int64_t chunk = idx >> 9;
+  const int i = chunk % MT; chunk /= MT;
+  const int kb = chunk % NKB; chunk /= NKB;
+  const int wave = (int)chunk;
+  const int row = 32 * (wave * MT + i) + (lane & 31);
+  const int col = 16 * kb + 8 * (lane >> 5) + e;
+  const float v = transpose ? src[(int64_t)col * W + row] : src[(int64_t)row * W + col];
+  dst[idx] = (__bf16)v;
+}
+
+__global__ void pack_fp32_kernel(const float* __restrict__ src, float* __restrict__ dst, int W, int transpose) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W * W) return;
+  const int MT = W / (32 * kWaves), NK8 = W / 8;
+  const int q = idx & 3;
+  const int lane = (idx >> 2) & 63;
+  int64_t chunk = idx >> 8;
+  const int i = chunk % MT; chunk /= MT;
+  const int j = chunk % NK8; chunk /= NK8;
+  const int wave = (int)chunk;
+  const int row = 32 * (wave * MT + i) + (lane & 31);
+  const int col = 8 * j + 2 * q + (lane >> 5);
+  dst[idx] = transpose ? src[(int64_t)col * W + row] : src[(int64_t)row * W + col];
+}
+
+hipError_t pack_matrix(const float* src, void* dst, int width, int mode, bool transpose, hipStream_t s) {
+  const int64_t n = (int64_t)width * width;
+  const int threads = 256;
+  const int blocks = (int)((n + threads - 1) / threads);
+  if (mode == kFP32)
+    hipLaunchKernelGGL(pack_fp32_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<float*>(dst), width,
+                       transpose ? 1 : 0);
+  else
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<__bf16*>(dst), width,
+                       transpose ? 1 : 0);
+  return hipGetLastError();
+}
+
+// Lane-major position of row R (see Bases).
+__host__ __device__ inline int lane_major_pos(int R, int W) {
+  const int MT = W / (32 * kWaves);
+  const int wave = R / (32 * MT), rem = R % (32 * MT);
+  const int i = rem / 32, g = (rem % 32) / 8, h = (rem % 8) / 4, r = rem % 4;
+  return ((wave * 2 + h) * MT + i) * 16 + 4 * g + r;
+}
+
+__global__ void pack_input_kernel(const float* __restrict__ W1, const float* __restrict__ b1, float* __restrict__ w1p,
+                                  int W) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= W) return;
+  float* o = w1p + lane_major_pos(r, W) * 12;
+  o[0] = W1[r * 9 + 0];
+  o[1] = W1[r * 9 + 1];
+  o[2] = W1[r * 9 + 2];
+  o[3] = b1[r];
+  for (int c = 3; c < 9; ++c) o[1 + c] = W1[r * 9 + c];
+  o[10] = 0.f;
+  o[11] = 0.f;
+}
+
+hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int width, hipStream_t s) {
+  hipLaunchKernelGGL(pack_input_kernel, dim3((width + 255) / 256), dim3(256), 0, s, W1, b1, w1p, width);
+  return hipGetLastError();
+}
+
+__global__ void pack_rows_kernel(const float* __restrict__ src, float* __restrict__ dst, int W, int nvec) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= W * nvec) return;
+  const int v = idx / W, r = idx % W;
+  dst[v * W + lane_major_pos(r, W)] = src[v * W + r];
+}
+
+hipError_t pack_row_vectors(const float* src, float* dst, int width, int nvec, hipStream_t s) {
+  const int n = width * nvec;
+  hipLaunchKernelGGL(pack_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, width, nvec);
+  return hipGetLastError();
+}
+
+__global__ void minkey_init_kernel(unsigned long long* k, int64_t K) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) k[i] = ~0ull;
+}
+
+hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t s) {
+  hipLaunchKernelGGL(minkey_init_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, minkey, K);
+  return hipGetLastError();
+}
+
+__global__ void minkey_decode_kernel(const unsigned long long* __restrict__ key, int64_t K, float* dmin,
+                                     int32_t* argmin, int64_t* kidx, int64_t* pidx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  const unsigned long long k = key[i];
+  const uint32_t o = (uint32_t)(k >> 32);
+  const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  if (dmin) dmin[i] = __uint_as_float(u);
+  // every knot of a launch receives at least one key; an untouched slot would
+  // decode to index 0 rather than an out-of-range point
+  const int32_t j = (k == ~0ull) ? 0 : (int32_t)(uint32_t)(k & 0xffffffffu);
+  if (argmin) argmin[i] = j;
+  if (kidx) kidx[i] = i;
+  if (pidx) pidx[i] = j;
+}
+
+hipError_t launch_minkey_decode(const unsigned long long* minkey, int64_t K, float* dmin, int32_t* argmin,
+                                int64_t* kidx, int64_t* pidx, hipStream_t s) {
+  hipLaunchKernelGGL(minkey_decode_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, minkey, K, dmin,
+                     argmin, kidx, pidx);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Launch
+// ----------------------------------------------------------------------------
+template <int W, int MODE, bool PAIRS>
+static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, int num_cu, hipStream_t s) {
+  constexpr int OCC = 1;
+  const int64_t ntiles = PAIRS ? (job.npairs + kTileQ - 1) / kTileQ
+                               : job.K * ((job.Np + kTileQ - 1) / kTileQ);
+  if (ntiles <= 0) return hipSuccess;
+  const int64_t slots = (int64_t)num_cu * OCC;
+  const int grid = (int)(ntiles < slots ? ntiles : slots);
+  hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC>), dim3(grid), dim3(kThreads), 0, s, net, job,
+                     want_grad ? 1 : 0, ntiles);
+  return hipGetLastError();
+}
+
+template <int W, int MODE>
+static hipError_t launch_m(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s) {
+  return pairs ? launch_t<W, MODE, true>(net, job, want_grad, num_cu, s)
+               : launch_t<W, MODE, false>(net, job, want_grad, num_cu, s);
+}
+
+template <int W>
+static hipError_t launch_w(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s) {
+  switch (net.mode) {
+    case kFP32: return launch_m<W, kFP32>(net, job, pairs, want_grad, num_cu, s);
+    case kBF16: return launch_m<W, kBF16>(net, job, pairs, want_grad, num_cu, s);
+    default: return launch_m<W, kBF16X2>(net, job, pairs, want_grad, num_cu, s);
+  }
+}
+
+hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s) {
+  if (net.width == 256) return launch_w<256>(net, job, pairs, want_grad, num_cu, s);
+  return launch_w<512>(net, job, pairs, want_grad, num_cu, s);
+}
+
+}  // namespace gcdf
