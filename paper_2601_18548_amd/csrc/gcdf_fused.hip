@@ -179,72 +179,99 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // ----------------------------------------------------------------------------
 // acc[i][nt] += M[rows of wave, :] x act[:, 32nt .. 32nt+31]
-// A fragments: this wave's stream, chunk (kstep, i) at ((kstep*MT + i)*64 + lane)*16 bytes.
-// The K loop is unrolled by two with two static fragment buffers: the loads for
-// step s+1 are in flight while the matrix cores work on step s.
+// A fragments come through a buffer descriptor (uniform, SGPRs) of the matrix's
+// packed stream: fragment (kstep, i) of this wave at byte
+// wave*stream_bytes + ((kstep*MT + i)*64 + lane)*16 -- one 32-bit VGPR offset
+// (voff = wave*stream_bytes + lane*16) serves every matrix and step; the step goes
+// in the scalar offset and i*1024 in the instruction's immediate.
+// Software pipeline: A is loaded two K steps ahead, B (LDS) one step ahead.
 // ----------------------------------------------------------------------------
+template <int MODE>
+struct BFrag {
+  bf16x8 h[2], l[2];
+  f32x4 f[2];
+};
+
 template <int W, int MODE>
-__device__ __forceinline__ void gemm_step(f32x16 (&acc)[Geo<W>::MT][2], const f32x4 (&af)[Geo<W>::MT],
-                                          const char* br) {
-  constexpr int MT = Geo<W>::MT;
+__device__ __forceinline__ void load_b(BFrag<MODE>& b, const char* br) {
   if constexpr (MODE == kFP32) {
-    f32x4 bf[2];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) bf[nt] = *reinterpret_cast<const f32x4*>(br + nt * 1024);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], bf[nt][q], acc[i][nt], 0, 0, 0);
+    for (int nt = 0; nt < 2; ++nt) b.f[nt] = *reinterpret_cast<const f32x4*>(br + nt * 1024);
   } else {
-    bf16x8 bh[2], bl[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      bh[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 1024);
-      if constexpr (MODE == kBF16X2) bl[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 1024);
-    }
-#pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, bh[nt], acc[i][nt], 0, 0, 0);
-    }
-    if constexpr (MODE == kBF16X2) {
-#pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, bl[nt], acc[i][nt], 0, 0, 0);
-      }
+      b.h[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 1024);
+      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 1024);
     }
   }
 }
 
 template <int W>
-__device__ __forceinline__ void load_frags(f32x4 (&af)[Geo<W>::MT], const char* __restrict__ a) {
+__device__ __forceinline__ void load_a(f32x4 (&af)[Geo<W>::MT], __amdgpu_buffer_rsrc_t rs, int voff, int step) {
+  const int soff = step * Geo<W>::MT * 1024;
 #pragma unroll
-  for (int i = 0; i < Geo<W>::MT; ++i) af[i] = *reinterpret_cast<const f32x4*>(a + i * 1024);
+  for (int i = 0; i < Geo<W>::MT; ++i)
+    af[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + i * 1024, soff, 0));
 }
 
-// A: this lane's position in the wave's fragment stream (stream base + lane*16).
+// One K step: for each M tile i, its MFMAs (hi then lo halves alternating over
+// the two column blocks, so accumulations into one tile are two MFMAs apart),
+// then at once the reload of a[i] for step `next` -- the fragment's registers
+// are free as soon as its last MFMA has issued.  The scheduling barriers keep
+// the compiler from sinking the loads to the end of the loop body.
 template <int W, int MODE>
-__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[Geo<W>::MT][2], const char* __restrict__ A,
+__device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[Geo<W>::MT][2], f32x4 (&af)[Geo<W>::MT],
+                                                const BFrag<MODE>& b, __amdgpu_buffer_rsrc_t rs, int voff,
+                                                int next) {
+  constexpr int MT = Geo<W>::MT;
+  const int soff = next * MT * 1024;
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    if constexpr (MODE == kFP32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], b.f[nt][q], acc[i][nt], 0, 0, 0);
+    } else {
+      const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.h[nt], acc[i][nt], 0, 0, 0);
+      if constexpr (MODE == kBF16X2) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.l[nt], acc[i][nt], 0, 0, 0);
+      }
+    }
+    af[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + i * 1024, soff, 0));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int W, int MODE>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* base) {
+  constexpr int bytes = W * W * (MODE == kFP32 ? 4 : 2);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+template <int W, int MODE>
+__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[Geo<W>::MT][2], __amdgpu_buffer_rsrc_t rs, int voff,
                                            const char* br) {
   constexpr int MT = Geo<W>::MT;
   constexpr int NS = (MODE == kFP32) ? Geo<W>::NK8 : Geo<W>::NKB;  // even
   f32x4 a0[MT], a1[MT];
-  load_frags<W>(a0, A);
+  BFrag<MODE> b0, b1;
+  load_a<W>(a0, rs, voff, 0);
+  load_a<W>(a1, rs, voff, 1);
+  load_b<W, MODE>(b0, br);
 #pragma unroll 1
   for (int s = 0; s < NS; s += 2) {
-    load_frags<W>(a1, A + MT * 1024);
-    gemm_step<W, MODE>(acc, a0, br);
-    const char* an = (s + 2 < NS) ? A + 2 * MT * 1024 : A + MT * 1024;
-    load_frags<W>(a0, an);
-    gemm_step<W, MODE>(acc, a1, br + 2048);
-    A += 2 * MT * 1024;
+    load_b<W, MODE>(b1, br + 2048);  // B of step s+1, one step ahead
+    __builtin_amdgcn_sched_barrier(0);
+    mma_step_reload<W, MODE>(acc, a0, b0, rs, voff, s + 2 < NS ? s + 2 : NS - 1);
+    load_b<W, MODE>(b0, s + 2 < NS ? br + 4096 : br);  // B of step s+2
+    __builtin_amdgcn_sched_barrier(0);
+    mma_step_reload<W, MODE>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
     br += 4096;
   }
 }
@@ -271,7 +298,7 @@ struct Bases {
   const float* w1;    // input layer rows (lane-major, 12 floats per row), at this lane's block
   const float* crow;  // per-knot input-layer constant (LDS, lane-major), at this lane's block
   const float* xin;   // xin + n0 * XIN_FLOATS
-  const char* A;      // lane offset inside a wave's fragment stream: wave*stream_bytes + lane*16
+  int voff;           // lane offset inside a matrix's fragment stream: wave*stream_bytes + lane*16
 };
 
 template <int W, int MODE, int L>
@@ -289,7 +316,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][nt][4 * g + r] = b4[r];
     }
-  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.fwd[L]) + (size_t)b.A, ln.act_r);
+  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
   __syncthreads();
   static_for<MT>([&](auto I) {
     static_for<4>([&](auto G) {
@@ -334,7 +361,7 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
-  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.bwd[L]) + (size_t)b.A, ln.act_r);
+  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
   __syncthreads();
   static_for<MT>([&](auto I) {
     static_for<4>([&](auto G) {
@@ -364,7 +391,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
-  layer_gemm<W, MODE>(acc, static_cast<const char*>(net.bwd[0]) + (size_t)b.A, ln.act_r);
+  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
 #pragma unroll
   for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -462,7 +489,7 @@ __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, c
   b.w1 = net.w1p + lblk * 12;
   b.crow = crow + lblk;
   b.xin = xin + ln.n0 * XF;
-  b.A = reinterpret_cast<const char*>((size_t)ln.wave * stream_bytes + (size_t)ln.lane * 16);
+  b.voff = (int)(ln.wave * stream_bytes) + ln.lane * 16;
 
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
   const int64_t qlimit = PAIRS ? job.npairs : job.Np;
