@@ -87,6 +87,72 @@ def time_mode(g, torch, wk, precision, steps, warmup):
     return dt, kms
 
 
+def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precision: str = "bf16x2",
+                budget_gib: float = 16.0, slots: int = 64, ring: int = 128):
+    """Poisson stream of trajectory-optimisation requests through gcdf_submit/gcdf_poll.
+
+    Each request: K ~ U{16..256} knots, Np ~ U{512..32768} patch points, full
+    outputs (d, J, per-knot min).  Inputs come from a pool of 32 device-resident
+    clouds / knot sets (sliced to the request's K and Np); outputs from a ring of
+    `ring` buffer sets, each reused only after its previous request completed.
+    Latency = completion seen by gcdf_poll - scheduled arrival time.
+    """
+    import numpy as np
+
+    from paper_2601_18548_amd import workloads as wl
+
+    w = wl.weights(256, seed)
+    ctx = g.Context(w.to_blob(), 256, precision, serve_mem_budget=int(budget_gib * (1 << 30)), serve_slots=slots)
+    trace = wl.serving_trace(n_requests, rate_hz, seed)
+    P = 32
+    pool_p = [torch.from_numpy(wl.points_patches(32768, seed + 10 + i)).cuda() for i in range(P)]
+    pool_k = [torch.from_numpy(wl.knots(256, seed + 100 + i)).cuda() for i in range(P)]
+    kmax, npmax = 256, 32768
+    outs = [(torch.empty(kmax * npmax, device="cuda"), torch.empty(kmax * npmax * 9, device="cuda"),
+             torch.empty(kmax, device="cuda"), torch.empty(kmax, dtype=torch.int32, device="cuda"))
+            for _ in range(min(ring, n_requests))]
+    torch.cuda.synchronize()
+    # warm the serving kernel once
+    t = ctx.submit(pool_k[0][:16], pool_p[0][:512], outs[0][0][:16 * 512].view(16, 512),
+                   outs[0][1][:16 * 512 * 9].view(16, 512, 9), outs[0][2][:16], outs[0][3][:16])
+    while not ctx.poll(t):
+        time.sleep(1e-4)
+    tickets, owner = {}, [None] * len(outs)
+    done_at = [None] * n_requests
+    t0 = time.perf_counter()
+    nxt = 0
+    pairs = 0
+    while nxt < n_requests or tickets:
+        now = time.perf_counter() - t0
+        if nxt < n_requests and now >= trace[nxt].arrival_s:
+            r = trace[nxt]
+            slot = nxt % len(outs)
+            if owner[slot] is not None and done_at[owner[slot]] is None:
+                pass  # buffer still in use: poll below, submit later (latency keeps counting)
+            else:
+                d, J, dm, am = outs[slot]
+                pi = nxt % P
+                tk = ctx.submit(pool_k[pi][:r.K], pool_p[pi][:r.Np], d[:r.K * r.Np].view(r.K, r.Np),
+                                J[:r.K * r.Np * 9].view(r.K, r.Np, 9), dm[:r.K], am[:r.K])
+                tickets[tk] = nxt
+                owner[slot] = nxt
+                pairs += r.K * r.Np
+                nxt += 1
+                continue
+        for tk in list(tickets):
+            if ctx.poll(tk):
+                done_at[tickets.pop(tk)] = time.perf_counter() - t0
+    elapsed = time.perf_counter() - t0
+    lat = np.array([done_at[i] - trace[i].arrival_s for i in range(n_requests)]) * 1e3
+    ctx.close()
+    mean_pairs = float(np.mean([r.K * r.Np for r in trace]))
+    return {"offered_req_per_s": rate_hz, "requests": n_requests, "precision": precision, "width": 256,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "completed_req_per_s": n_requests / elapsed,
+            "queries_per_s": pairs / elapsed, "offered_queries_per_s": rate_hz * mean_pairs,
+            "overloaded": bool(n_requests / elapsed < 0.95 * rate_hz)}
+
+
 def cpu_baseline(wk, seconds: float):
     import numpy as np
 
@@ -119,6 +185,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="skip the FP32 / pure-BF16 context runs")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving trace (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the query shards by knots or points "
@@ -131,6 +200,10 @@ def main():
     from paper_2601_18548_amd import workloads as wl
 
     g.library()  # fails loudly if the HIP library is missing
+    if args.serve_sweep:
+        for rate in [float(x) for x in args.serve_sweep.split(",")]:
+            print(json.dumps({"serving": serve_bench(g, torch, rate, args.serve_requests)}), flush=True)
+        return
     wk = wl.workload(args.workload)
     pairs = wk.K * wk.Np
     print("bench: workload %s (%d knots x %d points, width %d, %s), %d steps after %d warmup" %
@@ -183,6 +256,10 @@ def main():
                            "meets_1e-3": prec == "fp32"}
             print("bench: mode %s %.3f ms/step" % (prec, s * 1e3), file=sys.stderr, flush=True)
         out["modes"] = modes
+    if args.serve_requests > 0:
+        out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests)
+        print("bench: serving p50 %.1f ms p99 %.1f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wk, args.cpu_seconds)
     print(json.dumps(out), flush=True)

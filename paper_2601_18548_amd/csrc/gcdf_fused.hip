@@ -112,11 +112,14 @@ struct Geo {
 
 // ----------------------------------------------------------------------------
 // Activation tile in LDS (64 query columns).
-//  bf16 modes: hi plane then lo plane, element (k, n) at ((k/16)*64 + n)*16 + k%16.
-//  fp32 mode : element (k, n) at (((k/8)*64 + n)*2 + k%2)*4 + (k%8)/2.
-// Both put the 8 (bf16) or 4 (fp32) K-consecutive values one MFMA lane needs in
-// 16 contiguous bytes, and in both the B fragment of K step s and column block
-// nt starts at byte s*2048 + nt*1024, lane (n0, kh) at +n0*32 + kh*16.
+//  bf16 modes: hi plane then lo plane (W*128 bytes each).  Element (k, n) sits in
+//    the 16-byte group (k/16, (k%16)/8, n) at byte ((k/16)*2 + (k%16)/8)*1024 + n*16,
+//    position k%8 inside it.  The B fragment of K step s, column block nt is the
+//    2 KiB at s*2048, lane (n0, kh) reading the 16 bytes at kh*1024 + nt*512 + n0*16:
+//    every lane reads its own consecutive 16 bytes (no bank conflicts).
+//  fp32 mode : element (k, n) at (((k/8)*64 + n)*2 + k%2)*4 + (k%8)/2 floats; the
+//    B fragment of step s, block nt starts at s*2048 + nt*1024, lane (n0, kh) at
+//    +n0*32 + kh*16.
 //
 // Every address below is a per-lane base (computed once) plus a compile-time
 // constant, so the constants fold into the instructions' offset fields instead
@@ -138,33 +141,68 @@ struct Lane {
     rbase = 32 * MT * wave;
     if constexpr (MODE == kFP32) {
       act_w = act + 4 * (((rbase >> 3) * kTileQ + n0) * 8 + 2 * h);
+      act_r = act + n0 * 32 + kh * 16;
     } else {
-      act_w = act + 2 * (((rbase >> 4) * kTileQ + n0) * 16 + 4 * h);
+      act_w = act + (rbase >> 4) * 2048 + h * 1024 + n0 * 16;
+      act_r = act + kh * 1024 + n0 * 16;
     }
     act_w_lo = act_w + W * kTileQ * 2;
-    act_r = act + n0 * 32 + kh * 16;
   }
 };
 
-// Write rows R0..R0+3 (R0 = rbase + 32 i + 8 g + 4 h) of column n = 32 nt + n0.
+// Write rows R0..R0+3 (R0 = rbase + 32 i + 8 g + 4 h) of column n = 32 nt + n0 (fp32).
 template <int W, int MODE, int I, int G, int NT>
-__device__ __forceinline__ void act_store4(const Lane<W, MODE>& L, const float v[4]) {
+__device__ __forceinline__ void act_store4_fp32(const Lane<W, MODE>& L, const float v[4]) {
+  constexpr int off = (4 * I + G) * 2048 + NT * 1024;
+  *reinterpret_cast<f32x2*>(L.act_w + off) = f32x2{v[0], v[2]};       // rows R0, R0+2 (k%2 = 0)
+  *reinterpret_cast<f32x2*>(L.act_w + off + 16) = f32x2{v[1], v[3]};  // rows R0+1, R0+3 (k%2 = 1)
+}
+
+// Pack four floats into two dwords of bf16 (round to nearest even).
+__device__ __forceinline__ void pack4(const float v[4], uint32_t& d0, uint32_t& d1) {
+  bf16x4 h4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) h4[r] = (__bf16)v[r];
+  const f32x2 d = __builtin_bit_cast(f32x2, h4);
+  d0 = __float_as_uint(d[0]);
+  d1 = __float_as_uint(d[1]);
+}
+
+// bf16 modes: write rows of the group pair g = 2 GP, 2 GP + 1 (v[0..3] for g = 2 GP,
+// v[4..7] for g = 2 GP + 1) of column n = 32 nt + n0.  Lane (n0, h) holds k%8 in
+// [4h, 4h+4) of both 8-groups kh = 0 (g even) and kh = 1 (g odd); one swap across
+// the lane halves gives lane (n0, kh) the whole 8-group kh, written as 16 bytes.
+template <int W, int MODE, int I, int GP, int NT>
+__device__ __forceinline__ void act_store8(const Lane<W, MODE>& L, const float v[8]) {
+  constexpr int off = (2 * I + GP) * 2048 + NT * 512;
+  auto put = [&](char* base, const float* x) {
+    uint32_t e0, e1, o0, o1;  // e: g even (kh 0), o: g odd (kh 1)
+    pack4(x, e0, e1);
+    pack4(x + 4, o0, o1);
+    // lanes 32..63 of the first operand trade with lanes 0..31 of the second:
+    // afterwards lane (n0, kh) has k%8 in [0, 4) in the first and [4, 8) in the second
+    const auto s0 = __builtin_amdgcn_permlane32_swap(e0, o0, false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(e1, o1, false, false);
+    typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+    *reinterpret_cast<u32x4*>(base + off) = u32x4{s0[0], s1[0], s0[1], s1[1]};
+  };
+  put(L.act_w, v);
+  if constexpr (MODE == kBF16X2) {
+    float lo[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lo[r] = v[r] - (float)(__bf16)v[r];
+    put(L.act_w_lo, lo);
+  }
+}
+
+// Either layout: rows of groups g = 2 GP, 2 GP + 1 (see act_store8).
+template <int W, int MODE, int I, int GP, int NT>
+__device__ __forceinline__ void act_store_pair(const Lane<W, MODE>& L, const float v[8]) {
   if constexpr (MODE == kFP32) {
-    constexpr int off = (4 * I + G) * 2048 + NT * 1024;
-    *reinterpret_cast<f32x2*>(L.act_w + off) = f32x2{v[0], v[2]};       // rows R0, R0+2 (k%2 = 0)
-    *reinterpret_cast<f32x2*>(L.act_w + off + 16) = f32x2{v[1], v[3]};  // rows R0+1, R0+3 (k%2 = 1)
+    act_store4_fp32<W, MODE, I, 2 * GP, NT>(L, v);
+    act_store4_fp32<W, MODE, I, 2 * GP + 1, NT>(L, v + 4);
   } else {
-    constexpr int off = (2 * I + (G >> 1)) * 2048 + NT * 1024 + 16 * (G & 1);
-    bf16x4 h4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h4[r] = (__bf16)v[r];
-    *reinterpret_cast<bf16x4*>(L.act_w + off) = h4;
-    if constexpr (MODE == kBF16X2) {
-      bf16x4 l4;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) l4[r] = (__bf16)(v[r] - (float)h4[r]);
-      *reinterpret_cast<bf16x4*>(L.act_w_lo + off) = l4;
-    }
+    act_store8<W, MODE, I, GP, NT>(L, v);
   }
 }
 
@@ -200,8 +238,8 @@ __device__ __forceinline__ void load_b(BFrag<MODE>& b, const char* br) {
   } else {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      b.h[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 1024);
-      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 1024);
+      b.h[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 512);
+      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 512);
     }
   }
 }
@@ -319,24 +357,28 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
   __syncthreads();
   static_for<MT>([&](auto I) {
-    static_for<4>([&](auto G) {
-      f32x4 w5r = {0.f, 0.f, 0.f, 0.f};
-      if constexpr (L == 2) w5r = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 4 * G);
+    static_for<2>([&](auto GP) {
+      f32x4 w5r[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+      if constexpr (L == 2) {
+        w5r[0] = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP);
+        w5r[1] = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP + 4);
+      }
       static_for<2>([&](auto NT) {
-        float v[4];
+        float v[8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int q = 0; q < 8; ++q) {
+          const int j = 8 * GP + q;  // accumulator element: g = 2 GP + q/4, r = q%4
           float hv, dv;
-          silu_fwd(acc[I][NT][4 * G + r], hv, dv);
+          silu_fwd(acc[I][NT][j], hv, dv);
           if constexpr (L < 2) {
-            sp[L][I][NT][4 * G + r] = park(dv);
-            v[r] = hv;
+            sp[L][I][NT][j] = park(dv);
+            v[q] = hv;
           } else {
-            dpart[NT] += w5r[r] * hv;
-            v[r] = w5r[r] * dv;  // g4 = w5 * SiLU'(z4)
+            dpart[NT] += w5r[q >> 2][q & 3] * hv;
+            v[q] = w5r[q >> 2][q & 3] * dv;  // g4 = w5 * SiLU'(z4)
           }
         }
-        if (L < 2 || want_grad) act_store4<W, MODE, I, G, NT>(ln, v);
+        if (L < 2 || want_grad) act_store_pair<W, MODE, I, GP, NT>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -364,12 +406,15 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
   __syncthreads();
   static_for<MT>([&](auto I) {
-    static_for<4>([&](auto G) {
+    static_for<2>([&](auto GP) {
       static_for<2>([&](auto NT) {
-        float v[4];
+        float v[8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = acc[I][NT][4 * G + r] * unpark(sp[L - 1][I][NT][4 * G + r], acc[I][NT][4 * G + r]);
-        act_store4<W, MODE, I, G, NT>(ln, v);
+        for (int q = 0; q < 8; ++q) {
+          const int j = 8 * GP + q;
+          v[q] = acc[I][NT][j] * unpark(sp[L - 1][I][NT][j], acc[I][NT][j]);
+        }
+        act_store_pair<W, MODE, I, GP, NT>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -429,32 +474,31 @@ __device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W
   constexpr int MT = Geo<W>::MT;
   constexpr int XF = Geo<W>::XIN_FLOATS;
   static_for<MT>([&](auto I) {
-    static_for<4>([&](auto G) {
-      f32x4 wa[4], wb[4];
-      f32x2 wc[4];
-      float cr[4];
+    static_for<2>([&](auto GP) {
+      f32x4 wa[8], wb[8];
+      f32x2 wc[8];
+      float cr[8];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float* w = b.w1 + (16 * I + 4 * G + r) * 12;
-        wa[r] = *reinterpret_cast<const f32x4*>(w);
+      for (int q = 0; q < 8; ++q) {
+        const float* w = b.w1 + (16 * I + 8 * GP + q) * 12;
+        wa[q] = *reinterpret_cast<const f32x4*>(w);
         if constexpr (PAIRS) {
-          wb[r] = *reinterpret_cast<const f32x4*>(w + 4);
-          wc[r] = *reinterpret_cast<const f32x2*>(w + 8);
-          cr[r] = wa[r][3];
+          wb[q] = *reinterpret_cast<const f32x4*>(w + 4);
+          wc[q] = *reinterpret_cast<const f32x2*>(w + 8);
         } else {
-          cr[r] = b.crow[16 * I + 4 * G + r];
+          cr[q] = b.crow[16 * I + 8 * GP + q];
         }
       }
       static_for<2>([&](auto NT) {
         const float* x = b.xin + NT * 32 * XF;
-        float v[4];
+        float v[8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float c = cr[r];
-          if constexpr (PAIRS) c = arm_term(wa[r][3], wb[r][0], wb[r][1], wb[r][2], wb[r][3], wc[r][0], wc[r][1], x + 5);
-          v[r] = silu_only(input_preact(c, wa[r][0], wa[r][1], wa[r][2], x));
+        for (int q = 0; q < 8; ++q) {
+          float c = PAIRS ? 0.f : cr[q];
+          if constexpr (PAIRS) c = arm_term(wa[q][3], wb[q][0], wb[q][1], wb[q][2], wb[q][3], wc[q][0], wc[q][1], x + 5);
+          v[q] = silu_only(input_preact(c, wa[q][0], wa[q][1], wa[q][2], x));
         }
-        act_store4<W, MODE, I, G, NT>(ln, v);
+        act_store_pair<W, MODE, I, GP, NT>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -462,165 +506,348 @@ __device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W
 }
 
 // ----------------------------------------------------------------------------
-// The fused kernel.
+// Per-workgroup state and the body that processes one tile.
+// ----------------------------------------------------------------------------
+template <int W, int MODE>
+struct TileCtx {
+  char* act;
+  float* xin;   // [64][16]
+  float* crow;  // [W]
+  float* red;   // [4][10][64]
+  Lane<W, MODE> ln;
+  Bases<W, MODE> b;
+  __device__ __forceinline__ TileCtx(char* lds, const DevNet& net, int tid)
+      : act(lds), ln(lds, tid) {
+    using G = Geo<W>;
+    constexpr int MT = G::MT;
+    xin = reinterpret_cast<float*>(lds + G::ACT_BYTES);
+    crow = xin + kTileQ * G::XIN_FLOATS;
+    red = crow + W;
+    float* vec = red + kWaves * G::RED_VALS * kTileQ;  // [4][W]: b2, b3, b4, w_out
+    for (int i = tid; i < 4 * W; i += kThreads) vec[i] = i < 3 * W ? net.bh[i] : net.w5[i - 3 * W];
+    // bytes of one matrix's fragment stream per wave (1 KiB per fragment)
+    const size_t stream_bytes = (size_t)(MODE == kFP32 ? G::NK8 : G::NKB) * MT * 1024;
+    const int lblk = (ln.wave * 2 + ln.h) * MT * 16;  // this lane's block of lane-major rows
+    b.bh = vec + lblk;
+    b.w5 = vec + 3 * W + lblk;
+    b.w1 = net.w1p + lblk * 12;
+    b.crow = crow + lblk;
+    b.xin = xin + ln.n0 * G::XIN_FLOATS;
+    b.voff = (int)(ln.wave * stream_bytes) + ln.lane * 16;
+  }
+};
+
+// One tile: 64 points of knot kk starting at point q0 (dense), or pair-list
+// entries q0 .. q0+63 (pairs).  Every thread of the workgroup calls it; it ends
+// with a barrier, so consecutive calls can reuse the shared memory.
+template <int W, int MODE, bool PAIRS>
+__device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, int want_grad, int64_t kk,
+                                             int64_t q0, TileCtx<W, MODE>& tc) {
+  using G = Geo<W>;
+  constexpr int MT = G::MT;
+  constexpr int XF = G::XIN_FLOATS;
+  const int tid = threadIdx.x;
+  float* xin = tc.xin;
+  float* crow = tc.crow;
+  float* red = tc.red;
+  const Lane<W, MODE>& ln = tc.ln;
+  const Bases<W, MODE>& b = tc.b;
+  const int64_t qlimit = PAIRS ? job.npairs : job.Np;
+
+  // ---- prologue: base-frame points (+ per-knot arm term of the input layer) ----
+  if (tid < kTileQ) {
+    const int64_t q = q0 + tid;
+    const int64_t qc = q < qlimit ? q : qlimit - 1;   // clamp the ragged tail (never stored)
+    int64_t ki, pi;
+    if constexpr (PAIRS) {
+      ki = job.kidx ? job.kidx[qc] : qc;
+      pi = job.pidx ? job.pidx[qc] : qc;
+    } else {
+      ki = kk;
+      pi = qc;
+    }
+    const float* kn = job.knots + ki * kInDim;
+    const float* pt = job.points + pi * 3;
+    float sn, cs;
+    sincosf(kn[2], &sn, &cs);
+    const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
+    float* x = xin + tid * XF;
+    x[0] = cs * ux + sn * uy;
+    x[1] = -sn * ux + cs * uy;
+    x[2] = pt[2];
+    x[3] = cs;
+    x[4] = sn;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
+  }
+  if constexpr (!PAIRS) {
+    const float* kn = job.knots + kk * kInDim;
+    for (int r = tid; r < W; r += kThreads) {  // r: lane-major position
+      const float* w = net.w1p + r * 12;
+      crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], kn + 3);
+    }
+  }
+  __syncthreads();
+
+  fwd_input<W, MODE, PAIRS>(ln, b);
+  __syncthreads();
+
+  // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
+  float sp[2][MT][2][16];
+  float dpart[2] = {0.f, 0.f};
+  fwd_hidden<W, MODE, 0>(net, ln, b, sp, dpart, want_grad);
+  fwd_hidden<W, MODE, 1>(net, ln, b, sp, dpart, want_grad);
+  fwd_hidden<W, MODE, 2>(net, ln, b, sp, dpart, want_grad);
+
+  // ---- reverse sweep: W4^T, W3^T (into LDS), W2^T (into the input-layer gradient) ----
+  float epart[2][9];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) epart[nt][c] = 0.f;
+  if (want_grad) {
+    bwd_hidden<W, MODE, 2>(net, ln, b, sp);
+    bwd_hidden<W, MODE, 1>(net, ln, b, sp);
+    bwd_input<W, MODE, PAIRS>(net, ln, b, epart);
+  }
+
+  // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    dpart[nt] += __shfl_xor(dpart[nt], 32);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
+  }
+  if (ln.h == 0) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int n = 32 * nt + ln.n0;
+      red[(ln.wave * G::RED_VALS + 0) * kTileQ + n] = dpart[nt];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) red[(ln.wave * G::RED_VALS + 1 + c) * kTileQ + n] = epart[nt][c];
+    }
+  }
+  __syncthreads();
+
+  // ---- per query: final sums, chain rule, stores, per-knot minimum ----
+  if (tid < kTileQ) {
+    const int n = tid;
+    float vals[G::RED_VALS];
+#pragma unroll
+    for (int c = 0; c < G::RED_VALS; ++c) {
+      float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
+      vals[c] = sum;
+    }
+    const float dv = vals[0] + net.b5;
+    const int64_t q = q0 + n;
+    const bool valid = q < qlimit;
+    const int64_t out = PAIRS ? q : kk * job.Np + q;
+    if (valid && job.d) job.d[out] = dv;
+    if (valid && job.J && want_grad) {
+      const float* x = xin + n * XF;
+      const float cs = x[3], sn = x[4];
+      const float* e = vals + 1;
+      float* Jo = job.J + out * kInDim;
+      Jo[0] = -(cs * e[0] - sn * e[1]);
+      Jo[1] = -(sn * e[0] + cs * e[1]);
+      Jo[2] = e[0] * x[1] - e[1] * x[0];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) Jo[c] = e[c];
+    }
+    if constexpr (!PAIRS) {
+      if (job.minkey) {
+        unsigned long long key = valid ? (((unsigned long long)ordered_bits(dv) << 32) | (uint32_t)q) : ~0ull;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          unsigned long long o = __shfl_xor(key, off);
+          key = o < key ? o : key;
+        }
+        if (n == 0 && key != ~0ull) atomicMin(job.minkey + kk, key);
+      }
+    }
+  }
+  // The next tile's prologue rewrites xin and crow: every wave has passed the
+  // barrier above (crow's last reader), and xin's readers here are wave 0,
+  // which also writes it, in program order.
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// One-shot kernel: a persistent grid strides over all tiles of one job.
 // ----------------------------------------------------------------------------
 template <int W, int MODE, bool PAIRS, int OCC>
 __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
-  using G = Geo<W>;
-  constexpr int MT = G::MT;
-  constexpr int XF = G::XIN_FLOATS;
-  __shared__ __attribute__((aligned(16))) char lds[G::LDS_BYTES];
-  char* act = lds;
-  float* xin = reinterpret_cast<float*>(lds + G::ACT_BYTES);               // [64][16]
-  float* crow = xin + kTileQ * XF;                                         // [W]
-  float* red = crow + W;                                                   // [4][10][64]
-  float* vec = red + kWaves * G::RED_VALS * kTileQ;                        // [4][W]: b2, b3, b4, w_out
-
-  const int tid = threadIdx.x;
-  const Lane<W, MODE> ln(act, tid);
-  for (int i = tid; i < 4 * W; i += kThreads) vec[i] = i < 3 * W ? net.bh[i] : net.w5[i - 3 * W];
-  // bytes of one matrix's fragment stream per wave (1 KiB per fragment)
-  const size_t stream_bytes = (size_t)(MODE == kFP32 ? G::NK8 : G::NKB) * MT * 1024;
-  Bases<W, MODE> b;
-  const int lblk = (ln.wave * 2 + ln.h) * MT * 16;  // this lane's block of lane-major rows
-  b.bh = vec + lblk;
-  b.w5 = vec + 3 * W + lblk;
-  b.w1 = net.w1p + lblk * 12;
-  b.crow = crow + lblk;
-  b.xin = xin + ln.n0 * XF;
-  b.voff = (int)(ln.wave * stream_bytes) + ln.lane * 16;
-
+  __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
+  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
-  const int64_t qlimit = PAIRS ? job.npairs : job.Np;
-
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int64_t kk = 0, q0 = 0;
     if constexpr (PAIRS) {
-      q0 = tile * kTileQ;
+      process_tile<W, MODE, true>(net, job, want_grad, 0, tile * kTileQ, tc);
     } else {
-      kk = tile / nblk;
-      q0 = (tile - kk * nblk) * kTileQ;
+      const int64_t kk = tile / nblk;
+      process_tile<W, MODE, false>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
     }
+  }
+}
 
-    // ---- prologue: base-frame points (+ per-knot arm term of the input layer) ----
-    if (tid < kTileQ) {
-      const int64_t q = q0 + tid;
-      const int64_t qc = q < qlimit ? q : qlimit - 1;   // clamp the ragged tail (never stored)
-      int64_t ki, pi;
-      if constexpr (PAIRS) {
-        ki = job.kidx ? job.kidx[qc] : qc;
-        pi = job.pidx ? job.pidx[qc] : qc;
-      } else {
-        ki = kk;
-        pi = qc;
-      }
-      const float* kn = job.knots + ki * kInDim;
-      const float* pt = job.points + pi * 3;
-      float sn, cs;
-      sincosf(kn[2], &sn, &cs);
-      const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
-      float* x = xin + tid * XF;
-      x[0] = cs * ux + sn * uy;
-      x[1] = -sn * ux + cs * uy;
-      x[2] = pt[2];
-      x[3] = cs;
-      x[4] = sn;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
-    }
-    if constexpr (!PAIRS) {
-      const float* kn = job.knots + kk * kInDim;
-      for (int r = tid; r < W; r += kThreads) {  // r: lane-major position
-        const float* w = net.w1p + r * 12;
-        crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], kn + 3);
-      }
-    }
-    __syncthreads();
+// ----------------------------------------------------------------------------
+// Persistent serving kernel.  Requests are published by the host in sequence
+// order into ServeCtl (pinned host memory); every workgroup walks the sequence
+// with its own cursor and claims tiles with a compare-and-swap on the slot's
+// (seq, count) word, so a late workgroup can never claim tiles of a request
+// that has since been replaced in its slot.  The workgroup that finishes a
+// request's last tile decodes its per-knot minimum, restores the key scratch and
+// publishes completion with a system-scope release store.
+// ----------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T sys_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
-    fwd_input<W, MODE, PAIRS>(ln, b);
-    __syncthreads();
-
-    // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
-    float sp[2][MT][2][16];
-    float dpart[2] = {0.f, 0.f};
-    fwd_hidden<W, MODE, 0>(net, ln, b, sp, dpart, want_grad);
-    fwd_hidden<W, MODE, 1>(net, ln, b, sp, dpart, want_grad);
-    fwd_hidden<W, MODE, 2>(net, ln, b, sp, dpart, want_grad);
-
-    // ---- reverse sweep: W4^T, W3^T (into LDS), W2^T (into the input-layer gradient) ----
-    float epart[2][9];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) epart[nt][c] = 0.f;
-    if (want_grad) {
-      bwd_hidden<W, MODE, 2>(net, ln, b, sp);
-      bwd_hidden<W, MODE, 1>(net, ln, b, sp);
-      bwd_input<W, MODE, PAIRS>(net, ln, b, epart);
-    }
-
-    // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      dpart[nt] += __shfl_xor(dpart[nt], 32);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
-    }
-    if (ln.h == 0) {
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        const int n = 32 * nt + ln.n0;
-        red[(ln.wave * G::RED_VALS + 0) * kTileQ + n] = dpart[nt];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) red[(ln.wave * G::RED_VALS + 1 + c) * kTileQ + n] = epart[nt][c];
-      }
-    }
-    __syncthreads();
-
-    // ---- per query: final sums, chain rule, stores, per-knot minimum ----
-    if (tid < kTileQ) {
-      const int n = tid;
-      float vals[G::RED_VALS];
-#pragma unroll
-      for (int c = 0; c < G::RED_VALS; ++c) {
-        float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
-        vals[c] = sum;
-      }
-      const float dv = vals[0] + net.b5;
-      const int64_t q = q0 + n;
-      const bool valid = q < qlimit;
-      const int64_t out = PAIRS ? q : kk * job.Np + q;
-      if (valid && job.d) job.d[out] = dv;
-      if (valid && job.J && want_grad) {
-        const float* x = xin + n * XF;
-        const float cs = x[3], sn = x[4];
-        const float* e = vals + 1;
-        float* Jo = job.J + out * kInDim;
-        Jo[0] = -(cs * e[0] - sn * e[1]);
-        Jo[1] = -(sn * e[0] + cs * e[1]);
-        Jo[2] = e[0] * x[1] - e[1] * x[0];
-#pragma unroll
-        for (int c = 3; c < 9; ++c) Jo[c] = e[c];
-      }
-      if constexpr (!PAIRS) {
-        if (job.minkey) {
-          unsigned long long key = valid ? (((unsigned long long)ordered_bits(dv) << 32) | (uint32_t)q) : ~0ull;
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) {
-            unsigned long long o = __shfl_xor(key, off);
-            key = o < key ? o : key;
+template <int W, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, ServeCtl* ctl, ServeDev* dev,
+                                                          uint64_t first_seq, uint64_t idle_ticks) {
+  __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
+  __shared__ int64_t claim_info[3];  // seq (or -1 to exit), tile, finalize flag
+  __shared__ ServeDesc cur;
+  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
+  const int tid = threadIdx.x;
+  uint64_t seq = first_seq;  // this workgroup's cursor in the request sequence
+  uint64_t cur_seq = ~0ull;
+  uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
+  const uint32_t slots = sys_load(&ctl->slots);
+  // thread 0's view of the queue: host memory is read only when the cursor has
+  // caught up with the cached published count, or for a new request's size
+  uint64_t pub = 0, nt_seq = ~0ull;
+  int64_t ntiles = 0;
+  int backoff = 1;
+  while (true) {
+    if (tid == 0) {
+      int64_t got_seq = -1, got_tile = 0;
+      while (true) {
+        if (seq >= pub) pub = sys_load(&ctl->published);
+        if (seq < pub) {
+          const uint32_t s = (uint32_t)(seq % slots);
+          if (nt_seq != seq) {
+            ntiles = sys_load(&ctl->desc[s].ntiles);
+            nt_seq = seq;
           }
-          if (n == 0 && key != ~0ull) atomicMin(job.minkey + kk, key);
+          unsigned long long v = __hip_atomic_load(&dev->claim[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bool moved_on = false;
+          while (true) {
+            const uint64_t vs = v >> 32, vc = v & 0xffffffffull;
+            const uint64_t s32 = seq & 0xffffffffull;
+            unsigned long long nv;
+            int64_t t;
+            if (vs > s32) { moved_on = true; break; }  // slot already reused: seq is complete
+            if (vs < s32) { nv = (s32 << 32) | 1ull; t = 0; }   // first claim of request seq
+            else { if ((int64_t)vc >= ntiles) { moved_on = true; break; } nv = v + 1; t = (int64_t)vc; }
+            if (__hip_atomic_compare_exchange_strong(&dev->claim[s], &v, nv, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+              got_seq = (int64_t)seq;
+              got_tile = t;
+              break;
+            }
+          }
+          if (got_seq >= 0) break;
+          if (moved_on) ++seq;
+        } else {
+          if (sys_load(&ctl->stop) || __builtin_amdgcn_s_memrealtime() - idle_since > idle_ticks) break;
+          // idle: back off up to ~4 us between polls of host memory
+          for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(16);
+          backoff = backoff < 8 ? 2 * backoff : 8;
         }
       }
+      backoff = 1;
+      claim_info[0] = got_seq;
+      claim_info[1] = got_tile;
+      if (got_seq >= 0 && (uint64_t)got_seq != cur_seq) {
+        const ServeDesc* d = &ctl->desc[got_seq % slots];
+        cur.knots = sys_load(&d->knots);
+        cur.points = sys_load(&d->points);
+        cur.K = sys_load(&d->K);
+        cur.Np = sys_load(&d->Np);
+        cur.nblk = sys_load(&d->nblk);
+        cur.ntiles = sys_load(&d->ntiles);
+        cur.done_target = sys_load(&d->done_target);
+        cur.d = sys_load(&d->d);
+        cur.J = sys_load(&d->J);
+        cur.minkey = sys_load(&d->minkey);
+        cur.dmin = sys_load(&d->dmin);
+        cur.argmin = sys_load(&d->argmin);
+        cur.want_grad = sys_load(&d->want_grad);
+        cur.seq = (uint64_t)got_seq;
+      }
     }
-    // The next tile's prologue rewrites xin and crow: every wave has passed the
-    // barrier above (crow's last reader), and xin's readers here are wave 0,
-    // which also writes it, in program order.
     __syncthreads();
+    const int64_t gs = claim_info[0];
+    if (gs < 0) break;
+    cur_seq = (uint64_t)gs;
+    const int64_t t = claim_info[1];
+    Job job{};
+    job.knots = cur.knots;
+    job.points = cur.points;
+    job.K = cur.K;
+    job.Np = cur.Np;
+    job.d = cur.d;
+    job.J = cur.J;
+    job.minkey = cur.minkey;
+    const int64_t kk = t / cur.nblk;
+    process_tile<W, MODE, false>(net, job, cur.want_grad, kk, (t - kk * cur.nblk) * kTileQ, tc);
+    // every thread's stores and atomics of this tile are issued; publish them
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t s = (uint32_t)(cur.seq % slots);
+      const unsigned long long done =
+          __hip_atomic_fetch_add(&dev->done[s], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+      claim_info[2] = done == cur.done_target ? 1 : 0;
+    }
+    __syncthreads();
+    if (claim_info[2]) {
+      // last tile of the request: per-knot minimum, restore the key scratch
+      if (cur.dmin) {
+        for (int64_t k = tid; k < cur.K; k += kThreads) {
+          const unsigned long long key = __hip_atomic_load(cur.minkey + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t o = (uint32_t)(key >> 32);
+          const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+          cur.dmin[k] = __uint_as_float(u);
+          cur.argmin[k] = key == ~0ull ? 0 : (int32_t)(uint32_t)(key & 0xffffffffu);
+          cur.minkey[k] = ~0ull;
+        }
+      }
+      __threadfence_system();
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_store(&ctl->complete[cur.seq % slots], cur.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (tid == 0) idle_since = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+template <int W, int MODE>
+static hipError_t launch_serve_t(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq,
+                                 uint64_t idle_ticks, int num_cu, hipStream_t s) {
+  hipLaunchKernelGGL((serve_loop<W, MODE>), dim3(num_cu), dim3(kThreads), 0, s, net, ctl, dev, first_seq, idle_ticks);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq, uint64_t idle_ticks,
+                        int num_cu, hipStream_t s) {
+  if (net.width == 256) {
+    switch (net.mode) {
+      case kFP32: return launch_serve_t<256, kFP32>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+      case kBF16: return launch_serve_t<256, kBF16>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+      default: return launch_serve_t<256, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+    }
+  }
+  switch (net.mode) {
+    case kFP32: return launch_serve_t<512, kFP32>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+    case kBF16: return launch_serve_t<512, kBF16>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+    default: return launch_serve_t<512, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
   }
 }
 
@@ -719,6 +946,12 @@ hipError_t pack_row_vectors(const float* src, float* dst, int width, int nvec, h
 __global__ void minkey_init_kernel(unsigned long long* k, int64_t K) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < K) k[i] = ~0ull;
+}
+
+hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(minkey_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t s) {

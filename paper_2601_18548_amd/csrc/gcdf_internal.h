@@ -65,4 +65,48 @@ hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t
 hipError_t launch_minkey_decode(const unsigned long long* minkey, int64_t K, float* dmin, int32_t* argmin,
                                 int64_t* kidx, int64_t* pidx, hipStream_t s);
 
+// ----------------------------------------------------------------------------
+// Serving: a persistent kernel claims tiles of published requests.
+// ----------------------------------------------------------------------------
+constexpr int kMaxSlots = 256;
+
+// One request as the device sees it (written by the host before publication).
+struct ServeDesc {
+  uint64_t seq;         // request sequence number; slot = seq % slots
+  const float* knots;
+  const float* points;
+  int64_t K, Np, nblk, ntiles;
+  uint64_t done_target; // value of the slot's cumulative done counter when this request is complete
+  float* d;
+  float* J;
+  unsigned long long* minkey;  // [K], all ones on entry; restored to all ones on completion
+  float* dmin;
+  int32_t* argmin;
+  int32_t want_grad;
+  int32_t pad;
+};
+
+// Control block in pinned, coherent host memory (host <-> device).
+struct ServeCtl {
+  uint64_t published;              // number of requests published (host writes, release)
+  uint32_t stop;                   // host: exit when no work is claimable
+  uint32_t slots;                  // number of request slots in use (<= kMaxSlots)
+  uint64_t complete[kMaxSlots];    // seq + 1 of the last request completed in each slot (device writes)
+  ServeDesc desc[kMaxSlots];
+};
+
+// Claim / completion counters in device memory.
+struct ServeDev {
+  unsigned long long claim[kMaxSlots];  // (seq << 32) | tiles claimed of request seq
+  unsigned long long done[kMaxSlots];   // tiles finished in the slot, cumulative over its requests
+};
+
+// Launch the persistent serving kernel; it processes published requests from
+// sequence number first_seq on and returns once `stop` is set or no work has
+// appeared for idle_ticks of the 100 MHz real-time counter.
+hipError_t launch_serve(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq, uint64_t idle_ticks,
+                        int num_cu, hipStream_t s);
+
+hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
+
 }  // namespace gcdf
