@@ -153,6 +153,38 @@ gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket
  * (including one already reported complete), EDEVICE on a device error. */
 gcdf_status gcdf_poll(gcdf_ctx* ctx, uint64_t ticket);
 
+/* ------------------------------------------------------------------------ */
+/* Training form: gradients of the distance network's weights.               */
+/* ------------------------------------------------------------------------ */
+
+/* Sample i of a batch is the pair (knots[i], points[i]): one knot and one
+ * point per sample, the network evaluated on [R(yaw)^T (p - t), a] as in the
+ * query (the network of Sec. III-C, trained on (point, configuration) pairs). */
+typedef struct gcdf_trainer gcdf_trainer;
+
+/* Number of float32 parameters of a width-W, depth-4 network: the weight-blob
+ * payload W1 (W x 9), b1, W2, b2, W3, b3, W4, b4, w_out (1 x W), b_out. */
+int64_t gcdf_param_count(int32_t width);
+
+/* Create a trainer for width 256 with precision GCDF_FP32 or GCDF_BF16 (hidden
+ * layers on BF16 matrix cores from FP32 master weights) for batches up to
+ * max_batch samples.  Owns its device workspace (activation and gradient
+ * dumps, ~W * max_batch * 16 bytes for BF16).  EINVAL / ENOMEM / EDEVICE. */
+gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device, int64_t max_batch,
+                                gcdf_trainer** out);
+void gcdf_trainer_destroy(gcdf_trainer* tr);
+
+/* d[i] = network distance of sample i (device float32[B]).  params: device
+ * float32[gcdf_param_count(W)] (FP32 master weights, read at the call). */
+gcdf_status gcdf_train_forward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                               int64_t B, float* d, void* stream);
+
+/* grad_params (device float32[gcdf_param_count(W)], overwritten) =
+ * sum_i grad_d[i] * d d_i / d params: the reverse mode of the network, seeded
+ * with the per-sample loss gradient.  Deterministic (fixed reduction order). */
+gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                                int64_t B, const float* grad_d, float* grad_params, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,16 @@ def library() -> ctypes.CDLL:
     lib.gcdf_knot_min.restype = ctypes.c_int
     lib.gcdf_query.argtypes = [P, P, I64, P, I64, P, P, P, P, P, P]
     lib.gcdf_query.restype = ctypes.c_int
+    lib.gcdf_param_count.argtypes = [ctypes.c_int32]
+    lib.gcdf_param_count.restype = ctypes.c_int64
+    lib.gcdf_trainer_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, I64, ctypes.POINTER(P)]
+    lib.gcdf_trainer_create.restype = ctypes.c_int
+    lib.gcdf_trainer_destroy.argtypes = [P]
+    lib.gcdf_trainer_destroy.restype = None
+    lib.gcdf_train_forward.argtypes = [P, P, P, P, I64, P, P]
+    lib.gcdf_train_forward.restype = ctypes.c_int
+    lib.gcdf_train_backward.argtypes = [P, P, P, P, I64, P, P, P]
+    lib.gcdf_train_backward.restype = ctypes.c_int
     lib.gcdf_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.gcdf_submit.restype = ctypes.c_int
     lib.gcdf_poll.argtypes = [P, ctypes.c_uint64]
@@ -77,7 +87,8 @@ def library() -> ctypes.CDLL:
 
 
 EXPORTED = ["gcdf_create", "gcdf_destroy", "gcdf_last_error", "gcdf_eval", "gcdf_eval_grad",
-            "gcdf_knot_min", "gcdf_query", "gcdf_submit", "gcdf_poll"]
+            "gcdf_knot_min", "gcdf_query", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
+            "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward"]
 
 
 def _check(st: int, ctx=None):

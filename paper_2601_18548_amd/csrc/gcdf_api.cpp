@@ -125,7 +125,8 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   const size_t off_w1 = 0;
   const size_t off_bh = align(off_w1 + (size_t)W * 12 * 4);
   const size_t off_w5 = align(off_bh + (size_t)3 * W * 4);
-  const size_t off_m = align(off_w5 + (size_t)W * 4);
+  const size_t off_b5 = align(off_w5 + (size_t)W * 4);
+  const size_t off_m = align(off_b5 + 4);
   const size_t total = off_m + 6 * align(mbytes);
   const size_t ws = (size_t)c->cfg.max_knots * (8 + 8 + 8);
   float* staging = nullptr;
@@ -155,8 +156,6 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
       bl[l] = p + (size_t)W * W;
       p = bl[l] + W;
     }
-    c->net.b5 = 0.f;
-    std::memcpy(&c->net.b5, static_cast<const char*>(blob) + kHeader + 4 * (nfloat - 1), 4);
   }
   const float* w5src = bl[2] + W;
   float* w1p = reinterpret_cast<float*>(base + off_w1);
@@ -166,6 +165,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   if (e == hipSuccess) e = gcdf::pack_input_layer(W1, b1, w1p, W, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l) e = gcdf::pack_row_vectors(bl[l], bh + (size_t)l * W, W, 1, s);
   if (e == hipSuccess) e = gcdf::pack_row_vectors(w5src, w5, W, 1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + off_b5, staging + nfloat - 1, 4, hipMemcpyDeviceToDevice, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l) {
     void* f = base + off_m + (size_t)l * align(mbytes);
     void* b = base + off_m + (size_t)(3 + l) * align(mbytes);
@@ -186,6 +186,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   c->net.w1p = w1p;
   c->net.bh = bh;
   c->net.w5 = w5;
+  c->net.b5p = reinterpret_cast<const float*>(base + off_b5);
   if (cfg->serve_mem_budget > 0) {
     gcdf_status st = gcdf::server_start(c, cfg->serve_mem_budget, cfg->serve_slots > 0 ? cfg->serve_slots : 64, &c->server);
     if (st != GCDF_OK) {

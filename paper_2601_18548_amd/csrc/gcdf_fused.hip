@@ -320,6 +320,42 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 }
 
 // ----------------------------------------------------------------------------
+// Training: copy the LDS activation tile (hi plane for the BF16 modes) to a
+// feature-major array dst[f][q0 + n] (row stride ldb), zeros for the ragged tail.
+// All threads take part; each writes whole rows of 64 samples.
+// ----------------------------------------------------------------------------
+template <int W, int MODE>
+__device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {
+  for (int f = threadIdx.x; f < W; f += kThreads) {
+    if constexpr (MODE == kFP32) {
+      const float* a = reinterpret_cast<const float*>(act);
+      float* o = static_cast<float*>(dst) + (int64_t)f * ldb + q0;
+#pragma unroll 4
+      for (int n = 0; n < kTileQ; n += 4) {
+        f32x4 v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int nn = n + u;
+          v[u] = nn < nvalid ? a[(((f >> 3) * kTileQ + nn) * 2 + (f & 1)) * 4 + ((f & 7) >> 1)] : 0.f;
+        }
+        *reinterpret_cast<f32x4*>(o + n) = v;
+      }
+    } else {
+      const __bf16* a = reinterpret_cast<const __bf16*>(act);
+      __bf16* o = static_cast<__bf16*>(dst) + (int64_t)f * ldb + q0;
+      const int base = (((f >> 4) * 2 + ((f & 15) >> 3)) * 1024) / 2 + (f & 7);
+#pragma unroll 2
+      for (int n = 0; n < kTileQ; n += 8) {
+        bf16x8 v;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = n + u < nvalid ? a[base + (n + u) * 8] : (__bf16)0.f;
+        *reinterpret_cast<bf16x8*>(o + n) = v;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Layer bodies (compile-time layer index so every register array is static).
 // Element j of acc[i][nt] is row R = rbase + 32 i + 8 (j/4) + 4 (lane/32) + j%4
 // of the layer output and query column n = 32 nt + lane%32.
@@ -339,9 +375,23 @@ struct Bases {
   int voff;           // lane offset inside a matrix's fragment stream: wave*stream_bytes + lane*16
 };
 
-template <int W, int MODE, int L>
+// Dump of the current LDS tile for training (no-op when not training).
+struct TileDump {
+  const char* act;  // the LDS activation tile
+  void* H;
+  void* G;
+  int64_t ldb, q0;
+  int nvalid;
+  size_t layer_elems;  // W * ldb
+  size_t elem_bytes;
+  __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
+  __device__ __forceinline__ void* g(int l) const { return static_cast<char*>(G) + l * layer_elems * elem_bytes; }
+};
+
+template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                           float (&sp)[2][Geo<W>::MT][2][16], float (&dpart)[2], int want_grad) {
+                                           float (&sp)[2][Geo<W>::MT][2][16], float (&dpart)[2], int want_grad,
+                                           const TileDump& td) {
   constexpr int MT = Geo<W>::MT;
   f32x16 acc[MT][2];
 #pragma unroll
@@ -356,6 +406,22 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
     }
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
   __syncthreads();
+  if constexpr (TRAIN && L == 2) {
+    // training: the layer-4 activations h4 go through LDS first (for dL/dw_out)
+    static_for<MT>([&](auto I) {
+      static_for<2>([&](auto GP) {
+        static_for<2>([&](auto NT) {
+          float v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = silu_only(acc[I][NT][8 * GP + q]);
+          act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        });
+      });
+    });
+    __syncthreads();
+    dump_tile<W, MODE>(td.act, td.h(3), td.ldb, td.q0, td.nvalid);
+    __syncthreads();  // h4 fully read before g4 overwrites the tile
+  }
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
       f32x4 w5r[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
@@ -364,6 +430,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         w5r[1] = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP + 4);
       }
       static_for<2>([&](auto NT) {
+        const float seed = b.xin[NT * 32 * Geo<W>::XIN_FLOATS + 11];
         float v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -375,7 +442,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
             v[q] = hv;
           } else {
             dpart[NT] += w5r[q >> 2][q & 3] * hv;
-            v[q] = w5r[q >> 2][q & 3] * dv;  // g4 = w5 * SiLU'(z4)
+            v[q] = seed * (w5r[q >> 2][q & 3] * dv);  // g4 = seed * w5 * SiLU'(z4)
           }
         }
         if (L < 2 || want_grad) act_store_pair<W, MODE, I, GP, NT>(ln, v);
@@ -390,11 +457,14 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
     asm volatile("" : "+v"(dpart[0]), "+v"(dpart[1]));
   }
   __syncthreads();
+  // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
+  // overwritten only after the following K loop and its barrier
+  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid);
 }
 
-template <int W, int MODE, int L>
+template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                           const float (&sp)[2][Geo<W>::MT][2][16]) {
+                                           const float (&sp)[2][Geo<W>::MT][2][16], const TileDump& td) {
   constexpr int MT = Geo<W>::MT;
   f32x16 acc[MT][2];
 #pragma unroll
@@ -420,13 +490,14 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
     });
   });
   __syncthreads();
+  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.g(L), td.ldb, td.q0, td.nvalid);  // g3 or g2
 }
 
 // Last reverse layer: g1 = (W2^T g2) * SiLU'(z1) with z1 recomputed, then the
 // input-layer gradient e = W1^T g1 accumulated per lane in FP32.
-template <int W, int MODE, bool PAIRS>
+template <int W, int MODE, bool PAIRS, bool TRAIN>
 __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                          float (&epart)[2][9]) {
+                                          float (&epart)[2][9], const TileDump& td) {
   constexpr int MT = Geo<W>::MT;
   constexpr int XF = Geo<W>::XIN_FLOATS;
   f32x16 acc[MT][2];
@@ -437,6 +508,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
+  float g1keep[TRAIN ? MT : 1][2][16];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
 #pragma unroll
@@ -463,9 +535,26 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
           epart[nt][6] += wb[3] * g1;
           epart[nt][7] += wc[0] * g1;
           epart[nt][8] += wc[1] * g1;
+          if constexpr (TRAIN) g1keep[i][nt][4 * g + r] = g1;
         }
         __builtin_amdgcn_sched_barrier(0);
       }
+  if constexpr (TRAIN) {
+    // training: g1 through LDS to HBM (every wave has finished reading g2)
+    __syncthreads();
+    static_for<MT>([&](auto I) {
+      static_for<2>([&](auto GP) {
+        static_for<2>([&](auto NT) {
+          float v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = g1keep[I][NT][8 * GP + q];
+          act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        });
+      });
+    });
+    __syncthreads();
+    dump_tile<W, MODE>(td.act, td.g(0), td.ldb, td.q0, td.nvalid);
+  }
 }
 
 // Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.
@@ -540,7 +629,7 @@ struct TileCtx {
 // One tile: 64 points of knot kk starting at point q0 (dense), or pair-list
 // entries q0 .. q0+63 (pairs).  Every thread of the workgroup calls it; it ends
 // with a barrier, so consecutive calls can reuse the shared memory.
-template <int W, int MODE, bool PAIRS>
+template <int W, int MODE, bool PAIRS, bool TRAIN = false>
 __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, int want_grad, int64_t kk,
                                              int64_t q0, TileCtx<W, MODE>& tc) {
   using G = Geo<W>;
@@ -579,6 +668,17 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     x[4] = sn;
 #pragma unroll
     for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
+    // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact)
+    x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : 1.f;
+    if constexpr (PAIRS) {
+      if (job.dumpV) {
+        const bool ok = q < qlimit;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) job.dumpV[c * job.ldb + q] = ok ? x[c] : 0.f;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) job.dumpV[(3 + c) * job.ldb + q] = ok ? x[5 + c] : 0.f;
+      }
+    }
   }
   if constexpr (!PAIRS) {
     const float* kn = job.knots + kk * kInDim;
@@ -589,15 +689,27 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   }
   __syncthreads();
 
+  TileDump td{};
+  if constexpr (TRAIN) {
+    td.act = tc.act;
+    td.H = job.dumpH;
+    td.G = job.dumpG;
+    td.ldb = job.ldb;
+    td.q0 = q0;
+    td.nvalid = (int)(qlimit - q0 < kTileQ ? qlimit - q0 : kTileQ);
+    td.layer_elems = (size_t)W * job.ldb;
+    td.elem_bytes = MODE == kFP32 ? 4 : 2;
+  }
   fwd_input<W, MODE, PAIRS>(ln, b);
   __syncthreads();
+  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
 
   // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
   float sp[2][MT][2][16];
   float dpart[2] = {0.f, 0.f};
-  fwd_hidden<W, MODE, 0>(net, ln, b, sp, dpart, want_grad);
-  fwd_hidden<W, MODE, 1>(net, ln, b, sp, dpart, want_grad);
-  fwd_hidden<W, MODE, 2>(net, ln, b, sp, dpart, want_grad);
+  fwd_hidden<W, MODE, 0, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
+  fwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
+  fwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
 
   // ---- reverse sweep: W4^T, W3^T (into LDS), W2^T (into the input-layer gradient) ----
   float epart[2][9];
@@ -606,9 +718,9 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 #pragma unroll
     for (int c = 0; c < 9; ++c) epart[nt][c] = 0.f;
   if (want_grad) {
-    bwd_hidden<W, MODE, 2>(net, ln, b, sp);
-    bwd_hidden<W, MODE, 1>(net, ln, b, sp);
-    bwd_input<W, MODE, PAIRS>(net, ln, b, epart);
+    bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td);
+    bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td);
+    bwd_input<W, MODE, PAIRS, TRAIN>(net, ln, b, epart, td);
   }
 
   // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
@@ -640,7 +752,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       for (int w = 1; w < kWaves; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
       vals[c] = sum;
     }
-    const float dv = vals[0] + net.b5;
+    const float dv = vals[0] + *net.b5p;
     const int64_t q = q0 + n;
     const bool valid = q < qlimit;
     const int64_t out = PAIRS ? q : kk * job.Np + q;
@@ -677,7 +789,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 // ----------------------------------------------------------------------------
 // One-shot kernel: a persistent grid strides over all tiles of one job.
 // ----------------------------------------------------------------------------
-template <int W, int MODE, bool PAIRS, int OCC>
+template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false>
 __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
   __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
@@ -685,7 +797,7 @@ __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, c
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (PAIRS) {
-      process_tile<W, MODE, true>(net, job, want_grad, 0, tile * kTileQ, tc);
+      process_tile<W, MODE, true, TRAIN>(net, job, want_grad, 0, tile * kTileQ, tc);
     } else {
       const int64_t kk = tile / nblk;
       process_tile<W, MODE, false>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
@@ -993,8 +1105,16 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   if (ntiles <= 0) return hipSuccess;
   const int64_t slots = (int64_t)num_cu * OCC;
   const int grid = (int)(ntiles < slots ? ntiles : slots);
-  hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC>), dim3(grid), dim3(kThreads), 0, s, net, job,
-                     want_grad ? 1 : 0, ntiles);
+  if constexpr (PAIRS && W == 256) {  // training (weight gradients) is built for width 256
+    if (job.dumpH) {
+      hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3(kThreads), 0, s, net, job, 1,
+                         ntiles);
+      return hipGetLastError();
+    }
+  }
+  if (job.dumpH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC>), dim3(grid), dim3(kThreads), 0, s, net, job,
+                       want_grad ? 1 : 0, ntiles);
   return hipGetLastError();
 }
 
@@ -1016,6 +1136,154 @@ static hipError_t launch_w(const DevNet& net, const Job& job, bool pairs, bool w
 hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s) {
   if (net.width == 256) return launch_w<256>(net, job, pairs, want_grad, num_cu, s);
   return launch_w<512>(net, job, pairs, want_grad, num_cu, s);
+}
+
+// ----------------------------------------------------------------------------
+// Training: weight gradients.
+//
+// out[f][g] = sum_i G[f][i] H[g][i] over the batch, G and H feature-major with
+// row stride ldb.  Workgroup (tile, chunk) computes a 128 x 128 block of out over
+// one chunk of the batch with matrix cores (4 waves, 64 x 64 each) into
+// partial[chunk]; a second kernel adds the chunks in index order, so the result
+// does not depend on scheduling.
+// ----------------------------------------------------------------------------
+constexpr int kWgChunk = 2048;  // batch samples per chunk
+
+int wgrad_chunks(int64_t B) { return (int)((B + kWgChunk - 1) / kWgChunk); }
+
+template <int MODE>
+__global__ __launch_bounds__(256) void wgrad_gemm_kernel(const void* __restrict__ Gv, const void* __restrict__ Hv,
+                                                         int Wd, int64_t ldb, int64_t B, float* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tiles_n = Wd / 128;
+  const int tile = blockIdx.x % (tiles_n * tiles_n), chunk = blockIdx.x / (tiles_n * tiles_n);
+  const int f0 = (tile / tiles_n) * 128 + (wave >> 1) * 64;  // rows of out (G features)
+  const int g0 = (tile % tiles_n) * 128 + (wave & 1) * 64;   // cols of out (H features)
+  const int64_t i0 = (int64_t)chunk * kWgChunk;
+  const int64_t i1 = i0 + kWgChunk < B ? i0 + kWgChunk : B;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[a][c][j] = 0.f;
+  const int m = lane & 31, kh = lane >> 5;
+  if constexpr (MODE == kFP32) {
+    const float* G = static_cast<const float*>(Gv);
+    const float* H = static_cast<const float*>(Hv);
+    // lane (m, kh) takes 4 consecutive samples i .. i+3 with i = i8 + 4 kh; MFMA q pairs sample i8 + 4 kh + q
+    for (int64_t i8 = i0; i8 < i1; i8 += 8) {
+      f32x4 a[2], bb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = *reinterpret_cast<const f32x4*>(G + (int64_t)(f0 + 32 * t + m) * ldb + i8 + 4 * kh);
+        bb[t] = *reinterpret_cast<const f32x4*>(H + (int64_t)(g0 + 32 * t + m) * ldb + i8 + 4 * kh);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb)
+            acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ta][q], bb[tb][q], acc[ta][tb], 0, 0, 0);
+    }
+  } else {
+    const __bf16* G = static_cast<const __bf16*>(Gv);
+    const __bf16* H = static_cast<const __bf16*>(Hv);
+    for (int64_t i16 = i0; i16 < i1; i16 += 16) {
+      bf16x8 a[2], bb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = *reinterpret_cast<const bf16x8*>(G + (int64_t)(f0 + 32 * t + m) * ldb + i16 + 8 * kh);
+        bb[t] = *reinterpret_cast<const bf16x8*>(H + (int64_t)(g0 + 32 * t + m) * ldb + i16 + 8 * kh);
+      }
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb)
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ta], bb[tb], acc[ta][tb], 0, 0, 0);
+    }
+  }
+  // C layout: lane (n = lane%32, half h) holds rows 8 (j/4) + 4 h + j%4 of column n
+  float* out = partial + (int64_t)chunk * Wd * Wd;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = f0 + 32 * ta + 8 * (j >> 2) + 4 * kh + (j & 3);
+        const int col = g0 + 32 * tb + m;
+        out[(int64_t)row * Wd + col] = acc[ta][tb][j];
+      }
+}
+
+__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * n + i];
+  out[i] = s;
+}
+
+hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, int64_t ldb, int64_t B,
+                             float* partial, int nchunks, float* out, hipStream_t s) {
+  const int tiles = (width / 128) * (width / 128);
+  if (mode == kFP32)
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(tiles * nchunks), dim3(256), 0, s, G, H, width, ldb, B, partial);
+  else
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(tiles * nchunks), dim3(256), 0, s, G, H, width, ldb, B, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)width * width;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nchunks, n, out);
+  return hipGetLastError();
+}
+
+// One workgroup per row; each thread sums a fixed stride of samples, then a fixed
+// tree over the workgroup.
+template <bool BF>
+__global__ __launch_bounds__(256) void row_reduce_kernel(const void* __restrict__ Av, int64_t lda, int64_t B,
+                                                         const float* __restrict__ V, int64_t ldv, int C,
+                                                         float* __restrict__ out, float* __restrict__ bias) {
+  constexpr int kMaxC = 9;
+  __shared__ float red[kMaxC + 1][256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  float acc[kMaxC + 1];
+#pragma unroll
+  for (int c = 0; c <= kMaxC; ++c) acc[c] = 0.f;
+  for (int64_t i = t; i < B; i += 256) {
+    const float a = BF ? (float)static_cast<const __bf16*>(Av)[(int64_t)r * lda + i]
+                       : static_cast<const float*>(Av)[(int64_t)r * lda + i];
+    acc[kMaxC] += a;
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c)
+      if (c < C) acc[c] += a * V[(int64_t)c * ldv + i];
+  }
+#pragma unroll
+  for (int c = 0; c <= kMaxC; ++c) red[c][t] = acc[c];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int c = 0; c <= kMaxC; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int c = 0; c < C; ++c) out[(int64_t)r * C + c] = red[c][0];
+    if (bias) bias[r] = red[kMaxC][0];
+  }
+}
+
+hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
+                             int64_t ldv, int C, float* out, float* bias, hipStream_t s) {
+  if (C > 9) return hipErrorInvalidValue;
+  if (a_is_bf16)
+    hipLaunchKernelGGL(row_reduce_kernel<true>, dim3(rows), dim3(256), 0, s, A, lda, B, V, ldv, C, out, bias);
+  else
+    hipLaunchKernelGGL(row_reduce_kernel<false>, dim3(rows), dim3(256), 0, s, A, lda, B, V, ldv, C, out, bias);
+  return hipGetLastError();
 }
 
 }  // namespace gcdf

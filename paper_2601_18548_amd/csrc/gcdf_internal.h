@@ -21,7 +21,7 @@ struct DevNet {
   const float* w1p;   // [width][12]: W1[r][0..2], b1[r], W1[r][3..8], 0, 0
   const float* bh;    // [depth-1][width]: b2, b3, b4
   const float* w5;    // [width]
-  float b5;
+  const float* b5p;   // device pointer to the output bias
   const void* fwd[3]; // W2, W3, W4 as matrix-core A fragments (see pack_matrix)
   const void* bwd[3]; // W2^T, W3^T, W4^T, same layout
 };
@@ -39,6 +39,15 @@ struct Job {
   float* d;                  // dense: [K][Np]; pairs: [npairs]      (nullable)
   float* J;                  // dense: [K][Np][9]; pairs: [npairs][9] (nullable)
   unsigned long long* minkey;// dense only: [K] ordered (distance, index) keys (nullable)
+  // training (pairs mode): the reverse sweep is seeded with seed[i] = dL/dd_i instead
+  // of 1, and the tile's layer inputs and back-propagated gradients are written
+  // feature-major: dumpH[l][f][i] = h_{l+1}, dumpG[l][f][i] = dL/dz_{l+1} (l = 0..3),
+  // dumpV[c][i] = network input c (FP32); row stride ldb (a multiple of 64).
+  const float* seed;
+  void* dumpH;
+  void* dumpG;
+  float* dumpV;
+  int64_t ldb;
 };
 
 // Packed fragment bytes for one width x width matrix.
@@ -108,5 +117,19 @@ hipError_t launch_serve(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_
                         int num_cu, hipStream_t s);
 
 hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// Training: weight gradients from the dumped H / G (element type = bf16 for the
+// BF16 modes, float for FP32).
+// ----------------------------------------------------------------------------
+// out[f][g] = sum_{i < B} G[f][i] H[g][i] for f, g < width, via split-K partial
+// sums in `partial` (nchunks * width * width floats) reduced in a fixed order.
+hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, int64_t ldb, int64_t B, float* partial,
+                             int nchunks, float* out, hipStream_t s);
+int wgrad_chunks(int64_t B);
+// For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C, V row stride ldv)
+// and bias[r] = sum_i A[r][i] (bias may be NULL), i < B, fixed-order sums.
+hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
+                             int64_t ldv, int C, float* out, float* bias, hipStream_t s);
 
 }  // namespace gcdf

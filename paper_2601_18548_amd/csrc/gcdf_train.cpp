@@ -1,0 +1,219 @@
+// Training form of libgcdf: weight gradients behind the C ABI (include/gcdf.h).
+//
+// forward : the pair-list query kernel (sample i = knot i, point i), weights
+//           packed on the device from the FP32 master copy at every call;
+// backward: the same kernel in training mode -- forward recomputed per tile,
+//           reverse sweep seeded with dL/dd_i, layer inputs h_l and gradients
+//           g_l = dL/dz_l written feature-major -- then
+//             dW_l = G_l H_{l-1}^T       (matrix cores, split-K, fixed-order sum),
+//             dW_1 = G_1 V^T, db_l = sum_i G_l, dw_out = H_4 seed, db_out = sum seed
+//           (fixed-order row reductions).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gcdf.h"
+#include "gcdf_internal.h"
+#include "gcdf_serve.h"
+
+struct gcdf_trainer {
+  int W = 0, mode = 0, device = 0, num_cu = 0;
+  int64_t max_batch = 0, ldb = 0;
+  gcdf::DevNet net{};
+  void* wbuf = nullptr;
+  size_t mbytes = 0, off_m = 0;
+  void* dumpH = nullptr;
+  void* dumpG = nullptr;
+  float* dumpV = nullptr;
+  float* partial = nullptr;
+};
+
+namespace {
+
+gcdf_status tfail(gcdf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return gcdf::set_error(st, buf);
+}
+
+struct Offsets {
+  size_t W1, b1, Wl[3], bl[3], w5, b5, total;
+  explicit Offsets(int W) {
+    size_t o = 0;
+    W1 = o; o += (size_t)W * 9;
+    b1 = o; o += W;
+    for (int l = 0; l < 3; ++l) { Wl[l] = o; o += (size_t)W * W; bl[l] = o; o += W; }
+    w5 = o; o += W;
+    b5 = o; o += 1;
+    total = o;
+  }
+};
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int d) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != d) (void)hipSetDevice(d);
+  }
+  ~DevGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
+  const Offsets o(tr->W);
+  char* base = static_cast<char*>(tr->wbuf);
+  hipError_t e = gcdf::pack_input_layer(params + o.W1, params + o.b1, const_cast<float*>(tr->net.w1p), tr->W, s);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l)
+    e = gcdf::pack_row_vectors(params + o.bl[l], const_cast<float*>(tr->net.bh) + (size_t)l * tr->W, tr->W, 1, s);
+  if (e == hipSuccess) e = gcdf::pack_row_vectors(params + o.w5, const_cast<float*>(tr->net.w5), tr->W, 1, s);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    e = gcdf::pack_matrix(params + o.Wl[l], base + tr->off_m + (size_t)l * tr->mbytes, tr->W, tr->mode, false, s);
+    if (e == hipSuccess)
+      e = gcdf::pack_matrix(params + o.Wl[l], base + tr->off_m + (size_t)(3 + l) * tr->mbytes, tr->W, tr->mode, true, s);
+  }
+  tr->net.b5p = params + o.b5;
+  return e;
+}
+
+gcdf_status check(const gcdf_trainer* tr, const float* params, const float* knots, const float* points, int64_t B) {
+  if (!tr) return tfail(GCDF_EINVAL, "trainer is NULL");
+  if (!params || !knots || !points) return tfail(GCDF_EINVAL, "params/knots/points pointer is NULL");
+  if (B <= 0 || B > tr->max_batch) return tfail(GCDF_EINVAL, "batch %lld outside [1, %lld]", (long long)B, (long long)tr->max_batch);
+  return GCDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t gcdf_param_count(int32_t width) { return width > 0 ? (int64_t)Offsets(width).total : 0; }
+
+gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device, int64_t max_batch,
+                                gcdf_trainer** out) {
+  if (!out) return tfail(GCDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (width != 256) return tfail(GCDF_EINVAL, "training is built for width 256 (got %d)", width);
+  if (precision != GCDF_FP32 && precision != GCDF_BF16)
+    return tfail(GCDF_EINVAL, "training precision must be GCDF_FP32 or GCDF_BF16");
+  if (max_batch <= 0 || max_batch > ((int64_t)1 << 30)) return tfail(GCDF_EINVAL, "max_batch out of range");
+  int dev = device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return tfail(GCDF_EDEVICE, "no current HIP device");
+  DevGuard g(dev);
+  gcdf_trainer* tr = new gcdf_trainer;
+  tr->W = width;
+  tr->mode = precision;
+  tr->device = dev;
+  tr->max_batch = max_batch;
+  tr->ldb = (max_batch + gcdf::kTileQ - 1) / gcdf::kTileQ * gcdf::kTileQ;
+  hipError_t e = hipDeviceGetAttribute(&tr->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int W = width;
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  tr->mbytes = align(gcdf::packed_matrix_bytes(W, precision));
+  const size_t off_w1 = 0, off_bh = align((size_t)W * 12 * 4), off_w5 = off_bh + align((size_t)3 * W * 4);
+  tr->off_m = off_w5 + align((size_t)W * 4);
+  const size_t esz = precision == GCDF_FP32 ? 4 : 2;
+  const size_t dump = (size_t)4 * W * tr->ldb * esz;
+  if (e == hipSuccess) e = hipMalloc(&tr->wbuf, tr->off_m + 6 * tr->mbytes);
+  if (e == hipSuccess) e = hipMalloc(&tr->dumpH, dump);
+  if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&tr->partial), (size_t)gcdf::wgrad_chunks(max_batch) * W * W * 4);
+  if (e != hipSuccess) {
+    gcdf_trainer_destroy(tr);
+    return tfail(GCDF_ENOMEM, "trainer allocation failed: %s", hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(tr->wbuf);
+  tr->net.width = W;
+  tr->net.mode = precision;
+  tr->net.w1p = reinterpret_cast<float*>(base + off_w1);
+  tr->net.bh = reinterpret_cast<float*>(base + off_bh);
+  tr->net.w5 = reinterpret_cast<float*>(base + off_w5);
+  for (int l = 0; l < 3; ++l) {
+    tr->net.fwd[l] = base + tr->off_m + (size_t)l * tr->mbytes;
+    tr->net.bwd[l] = base + tr->off_m + (size_t)(3 + l) * tr->mbytes;
+  }
+  *out = tr;
+  return GCDF_OK;
+}
+
+void gcdf_trainer_destroy(gcdf_trainer* tr) {
+  if (!tr) return;
+  DevGuard g(tr->device);
+  (void)hipFree(tr->wbuf);
+  (void)hipFree(tr->dumpH);
+  (void)hipFree(tr->dumpG);
+  (void)hipFree(tr->dumpV);
+  (void)hipFree(tr->partial);
+  delete tr;
+}
+
+gcdf_status gcdf_train_forward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                               int64_t B, float* d, void* stream) {
+  gcdf_status st = check(tr, params, knots, points, B);
+  if (st != GCDF_OK) return st;
+  if (!d) return tfail(GCDF_EINVAL, "d is NULL");
+  DevGuard g(tr->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pack(tr, params, s);
+  gcdf::Job job{};
+  job.knots = knots;
+  job.points = points;
+  job.K = B;
+  job.Np = B;
+  job.npairs = B;
+  job.d = d;
+  if (e == hipSuccess) e = gcdf::launch_fused(tr->net, job, true, false, tr->num_cu, s);
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_forward: %s", hipGetErrorString(e));
+}
+
+gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                                int64_t B, const float* grad_d, float* grad, void* stream) {
+  gcdf_status st = check(tr, params, knots, points, B);
+  if (st != GCDF_OK) return st;
+  if (!grad_d || !grad) return tfail(GCDF_EINVAL, "grad_d or grad_params is NULL");
+  DevGuard g(tr->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = tr->W;
+  const Offsets o(W);
+  const size_t esz = tr->mode == GCDF_FP32 ? 4 : 2;
+  const size_t layer = (size_t)W * tr->ldb * esz;
+  auto H = [&](int l) { return static_cast<const char*>(tr->dumpH) + l * layer; };
+  auto G = [&](int l) { return static_cast<const char*>(tr->dumpG) + l * layer; };
+  const bool bf = tr->mode != GCDF_FP32;
+  hipError_t e = pack(tr, params, s);
+  gcdf::Job job{};
+  job.knots = knots;
+  job.points = points;
+  job.K = B;
+  job.Np = B;
+  job.npairs = B;
+  job.seed = grad_d;
+  job.dumpH = tr->dumpH;
+  job.dumpG = tr->dumpG;
+  job.dumpV = tr->dumpV;
+  job.ldb = tr->ldb;
+  if (e == hipSuccess) e = gcdf::launch_fused(tr->net, job, true, true, tr->num_cu, s);
+  const int nch = gcdf::wgrad_chunks(B);
+  const int gmode = bf ? gcdf::kBF16 : gcdf::kFP32;
+  // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4
+  for (int l = 0; l < 3 && e == hipSuccess; ++l)
+    e = gcdf::launch_wgrad_gemm(G(l + 1), H(l), W, gmode, tr->ldb, B, tr->partial, nch, grad + o.Wl[l], s);
+  // input layer: dW1 = G_1 V^T, db1 = sum G_1
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(G(0), bf, tr->ldb, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, s);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l)
+    e = gcdf::launch_row_reduce(G(l + 1), bf, tr->ldb, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], s);
+  // output layer: dw_out = H_4 seed, db_out = sum seed
+  if (e == hipSuccess) e = gcdf::launch_row_reduce(H(3), bf, tr->ldb, W, B, grad_d, 0, 1, grad + o.w5, nullptr, s);
+  if (e == hipSuccess) e = gcdf::launch_row_reduce(grad_d, false, 0, 1, B, nullptr, 0, 0, nullptr, grad + o.b5, s);
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
+}
+
+}  // extern "C"

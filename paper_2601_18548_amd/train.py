@@ -1,0 +1,121 @@
+"""Training form: the distance network's weight gradients behind torch.autograd.
+
+``GcdfNet.apply(params, knots, points, trainer)`` returns the distances of the
+samples (knot i, point i); its backward calls ``gcdf_train_backward``, whose
+HIP kernels run the network's reverse mode seeded with dL/dd and reduce the
+weight gradients over the batch.  ``params`` is one flat FP32 tensor in the
+weight-blob order (W1, b1, ..., w_out, b_out); the optimiser keeps it as the
+FP32 master copy, and the kernels pack it (to BF16 for the BF16 precision) at
+every call.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import BF16, FP32, PRECISIONS, GcdfError, _check, _stream, library
+
+
+def param_count(width: int) -> int:
+    return int(library().gcdf_param_count(width))
+
+
+def flat_params(weights, device="cuda"):
+    """Flat FP32 parameter tensor (blob order) from a workloads.Weights."""
+    import torch
+
+    return torch.from_numpy(np.concatenate([a.ravel() for a in weights.flat_params()]).astype(np.float32)).to(device)
+
+
+class Trainer:
+    def __init__(self, width: int = 256, precision="bf16", max_batch: int = 65536, device: int = 0):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(library().gcdf_trainer_create(width, prec, device, max_batch, ctypes.byref(h)))
+        self._h, self.width, self.precision, self.max_batch = h, width, prec, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().gcdf_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, params, knots, points, d=None, stream=None):
+        import torch
+
+        B = knots.shape[0]
+        if d is None:
+            d = torch.empty(B, dtype=torch.float32, device=knots.device)
+        _check(library().gcdf_train_forward(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
+                                            d.data_ptr(), _stream(stream)))
+        return d
+
+    def backward(self, params, knots, points, grad_d, grad=None, stream=None):
+        import torch
+
+        B = knots.shape[0]
+        if grad is None:
+            grad = torch.empty_like(params)
+        _check(library().gcdf_train_backward(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
+                                             grad_d.data_ptr(), grad.data_ptr(), _stream(stream)))
+        return grad
+
+
+def _checked(t, dtype_name):
+    import torch
+
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float32):
+        raise ValueError("%s must be a contiguous float32 CUDA tensor" % dtype_name)
+    return t
+
+
+def _make_function():
+    import torch
+
+    class GcdfNet(torch.autograd.Function):
+        """d = network(params)(samples); backward -> d loss / d params only."""
+
+        @staticmethod
+        def forward(ctx, params, knots, points, trainer):
+            _checked(params, "params")
+            _checked(knots, "knots")
+            _checked(points, "points")
+            d = trainer.forward(params, knots, points)
+            ctx.save_for_backward(params, knots, points)
+            ctx.trainer = trainer
+            return d
+
+        @staticmethod
+        def backward(ctx, grad_d):
+            params, knots, points = ctx.saved_tensors
+            g = ctx.trainer.backward(params, knots, points, grad_d.contiguous().float())
+            return g, None, None, None
+
+    return GcdfNet
+
+
+_fn = None
+
+
+def gcdf_net(params, knots, points, trainer):
+    """Differentiable network distances of the samples (knot i, point i)."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.apply(params, knots, points, trainer)
+
+
+def mse_step(params, opt, trainer, knots, points, targets):
+    """One training step: MSE loss through the HIP network, backward, optimiser step."""
+    opt.zero_grad(set_to_none=False)
+    d = gcdf_net(params, knots, points, trainer)
+    loss = ((d - targets) ** 2).mean()
+    loss.backward()
+    opt.step()
+    return loss

@@ -1,0 +1,117 @@
+"""Training form on the GPU: weight gradients vs the FP64 oracle, finite
+differences of the GPU loss, determinism, autograd + Adam.
+
+Tolerances: FP32 mode, per parameter array, |g - g_ref| / |g_ref| <= 1e-4
+(FP32 accumulation over a few hundred samples); BF16 mode (activations and
+gradients rounded to BF16 for the matrix cores) <= 5e-2, printed.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_18548_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NAMES = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "w_out", "b_out"]
+
+
+@pytest.fixture(scope="module")
+def tr_mod():
+    import paper_2601_18548_amd as g
+    from paper_2601_18548_amd import train
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    g.library()
+    return train
+
+
+def batch(B, seed):
+    k, p, noise = wl.training_batch(B, seed)
+    y = np.random.default_rng(seed + 5).normal(0, 1, B).astype(np.float32)
+    return k, p, y
+
+
+def gpu_grads(tr_mod, precision, w, k, p, y):
+    trainer = tr_mod.Trainer(256, precision, max_batch=len(k))
+    params = tr_mod.flat_params(w)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    d = trainer.forward(params, kt, pt)
+    gd = (2.0 * (d - torch.from_numpy(y).cuda()) / len(k)).contiguous()
+    g = trainer.backward(params, kt, pt, gd)
+    torch.cuda.synchronize()
+    return trainer, params, kt, pt, d.cpu().numpy(), g.cpu().numpy()
+
+
+def split(flat, w):
+    out, off = [], 0
+    for a in w.flat_params():
+        out.append(flat[off:off + a.size].reshape(a.shape))
+        off += a.size
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 5e-2)])
+def test_weight_gradients_match_oracle(tr_mod, oracle_mod, precision, tol):
+    w = wl.weights(256, seed=31, bf16_hidden=False)  # FP32 master weights, off the BF16 grid
+    k, p, y = batch(300, 3)  # ragged: not a multiple of 64
+    _, _, _, _, d, g = gpu_grads(tr_mod, precision, w, k, p, y)
+    loss_ref, gref = oracle_mod.mse_grad(w.to_blob(), k.astype(np.float64), p.astype(np.float64), y)
+    for name, a, b in zip(NAMES, split(g, w), gref):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("%s %-5s rel err %.2e" % (precision, name, err), flush=True)
+        assert np.all(np.isfinite(a))
+        assert err <= tol, name
+
+
+def test_backward_is_deterministic(tr_mod):
+    w = wl.weights(256, seed=32, bf16_hidden=False)
+    k, p, y = batch(2048 + 37, 4)
+    trainer, params, kt, pt, d, g1 = gpu_grads(tr_mod, "bf16", w, k, p, y)
+    gd = (2.0 * (torch.from_numpy(d).cuda() - torch.from_numpy(y).cuda()) / len(k)).contiguous()
+    g2 = trainer.backward(params, kt, pt, gd).cpu().numpy()
+    assert np.array_equal(g1, g2)
+
+
+def test_gradient_matches_finite_differences_of_gpu_loss(tr_mod):
+    w = wl.weights(256, seed=33, bf16_hidden=False)
+    k, p, y = batch(512, 5)
+    trainer, params, kt, pt, d, g = gpu_grads(tr_mod, "fp32", w, k, p, y)
+    yt = torch.from_numpy(y).cuda()
+
+    def loss(pv):
+        dd = trainer.forward(pv, kt, pt).double()
+        return float(((dd - yt.double()) ** 2).mean())
+
+    idx = np.argsort(-np.abs(g))[:12]  # the largest components: well above FP32 noise
+    h = 1e-3
+    for i in idx:
+        pp, pm = params.clone(), params.clone()
+        pp[i] += h
+        pm[i] -= h
+        fd = (loss(pp) - loss(pm)) / (2 * h)
+        assert abs(fd - g[i]) <= 2e-3 * abs(g[i]) + 1e-5, (i, fd, g[i])
+
+
+def test_autograd_function_and_adam_reduce_the_loss(tr_mod):
+    teacher = wl.weights(256, seed=34, bf16_hidden=False)
+    student = wl.weights(256, seed=35, bf16_hidden=False)
+    B = 4096
+    k, p, noise = wl.training_batch(B, 6)
+    trainer = tr_mod.Trainer(256, "bf16", max_batch=B)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    with torch.no_grad():
+        y = trainer.forward(tr_mod.flat_params(teacher), kt, pt) + torch.from_numpy(noise).cuda()
+    params = tr_mod.flat_params(student).requires_grad_(True)
+    # autograd gradient == direct backward
+    d = tr_mod.gcdf_net(params, kt, pt, trainer)
+    loss = ((d - y) ** 2).mean()
+    loss.backward()
+    gd = (2.0 * (d.detach() - y) / B).contiguous()
+    direct = trainer.backward(params.detach(), kt, pt, gd)
+    assert torch.equal(params.grad, direct)
+    opt = torch.optim.Adam([params], lr=5e-3)
+    losses = [tr_mod.mse_step(params, opt, trainer, kt, pt, y).item() for _ in range(30)]
+    print("loss %.4f -> %.4f" % (losses[0], losses[-1]), flush=True)
+    assert losses[-1] < 0.5 * losses[0]
