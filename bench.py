@@ -12,7 +12,9 @@ Prints one JSON line: pairs (queries) per second, plus
   roofline     : the fused kernel's algorithmic TFLOP/s vs the dense BF16 peak
                  (launch durations from HIP events on the launch stream);
   cpu_baseline : the FP64 CPU oracle on a bounded sample of the same pairs;
-  modes        : the same workload in FP32 and pure BF16 (context, same metric).
+  modes        : the same workload in FP32 and pure BF16 (context, same metric);
+  serving      : p50 / p99 latency of a Poisson request trace through gcdf_submit;
+  training     : steps/s of the width-256 training step (batch 65,536, Adam).
 """
 from __future__ import annotations
 
@@ -153,6 +155,39 @@ def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precis
             "overloaded": bool(n_requests / elapsed < 0.95 * rate_hz)}
 
 
+def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
+    """Training step of the width-256 network: MSE against a seeded teacher's
+    distances plus N(0, 1e-3) noise, hand-written forward/backward behind
+    torch.autograd, Adam (lr 0.005) on FP32 master weights, BF16 matrix cores."""
+    from paper_2601_18548_amd import train
+    from paper_2601_18548_amd import workloads as wl
+
+    teacher = wl.weights(width, seed=501, bf16_hidden=False)
+    student = wl.weights(width, seed=502, bf16_hidden=False)
+    k, p, noise = wl.training_batch(batch, 503)
+    tr = train.Trainer(width, "bf16", max_batch=batch)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    with torch.no_grad():
+        y = tr.forward(train.flat_params(teacher), kt, pt) + torch.from_numpy(noise).cuda()
+    params = train.flat_params(student).requires_grad_(True)
+    opt = torch.optim.Adam([params], lr=5e-3, betas=(0.9, 0.999))
+    loss0 = None
+    for _ in range(warmup):
+        loss0 = train.mse_step(params, opt, tr, kt, pt, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = train.mse_step(params, opt, tr, kt, pt, y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # algorithmic work per sample: forward 6 W^2, reverse 6 W^2, weight gradients 6 W^2
+    fl = 18 * width * width * batch
+    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "samples_per_s": batch * steps / el,
+            "batch": batch, "width": width, "precision": "bf16 (FP32 master weights, FP32 accumulate)",
+            "tflops_algorithmic": fl * steps / el / 1e12,
+            "loss_first": float(loss0.item()) if loss0 is not None else None, "loss_last": float(loss.item())}
+
+
 def cpu_baseline(wk, seconds: float):
     import numpy as np
 
@@ -187,6 +222,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true", help="skip the FP32 / pure-BF16 context runs")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -260,6 +296,9 @@ def main():
         out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests)
         print("bench: serving p50 %.1f ms p99 %.1f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]),
               file=sys.stderr, flush=True)
+    if args.train_steps > 0:
+        out["training"] = train_bench(torch, args.train_steps, 3)
+        print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wk, args.cpu_seconds)
     print(json.dumps(out), flush=True)
