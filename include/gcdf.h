@@ -123,6 +123,64 @@ gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float
                        float* d, float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Obstacle partitions and the sparse constraint Jacobian.                   */
+/*                                                                           */
+/* Sec. IV-A of the paper: the obstacle points are split into N overlapping  */
+/* partitions I_{M,i}, one per time step, holding the points within a range  */
+/* of that step's reference base position; the GCDF constraints are stacked  */
+/* knot by knot into c_gcdf (length m_1 + ... + m_N), and each knot's dense  */
+/* gradient rows are placed by the projection P_i at the columns of q_i      */
+/* inside the state x_i = [q_i, v_i] of the (sum m_i) x 2Nn Jacobian.        */
+/* Partitions are in CSR form: offsets int64[N+1] (offsets[0] = 0), idx      */
+/* int32[offsets[N]] with the points of partition i, ascending, at           */
+/* idx[offsets[i] .. offsets[i+1]-1].  All arrays are device memory owned by */
+/* the caller; the calls are asynchronous on `stream`.                       */
+/* ------------------------------------------------------------------------ */
+
+/* Partition sizes.  Reference base position i is (ref[i*ref_stride],
+ * ref[i*ref_stride+1]) (ref_stride = 9 takes the (x, y) of a knots array);
+ * point j (points float32[Np][3]) is in partition i when
+ * dx*dx + dy*dy <= radius*radius, evaluated in float32 with every product and
+ * the sum rounded (no fused multiply-add), dx = px - x_i, dy = py - y_i.
+ * Writes offsets int64[N+1].  The caller reads offsets[N] (the total) to size
+ * idx.  EINVAL: NULL pointers, N <= 0, Np <= 0 or > 2^31 - 1, ref_stride < 2,
+ * radius negative or not finite. */
+gcdf_status gcdf_partition_count(gcdf_ctx* ctx, const float* ref, int64_t N, int64_t ref_stride,
+                                 const float* points, int64_t Np, float radius, int64_t* offsets,
+                                 void* stream);
+
+/* Partition members: idx[offsets[i] + k] = the k-th point (ascending index)
+ * of partition i, for offsets from gcdf_partition_count with the same
+ * arguments.  Positions >= capacity are not written (compare offsets[N] with
+ * capacity).  EINVAL as gcdf_partition_count, or idx NULL with capacity > 0. */
+gcdf_status gcdf_partition_fill(gcdf_ctx* ctx, const float* ref, int64_t N, int64_t ref_stride,
+                                const float* points, int64_t Np, float radius, const int64_t* offsets,
+                                int32_t* idx, int64_t capacity, void* stream);
+
+/* The stacked constraint vector and its dense gradient rows over CSR
+ * partitions: row r (0 <= r < total) pairs knot i, the last i with
+ * offsets[i] <= r (empty partitions are skipped), with point idx[r];
+ * c[r] (float32[total]) = d of that pair and, if J != NULL, J[r][0..8]
+ * (float32[total][9]) = its configuration gradient, bitwise equal to the
+ * entries gcdf_eval_grad gives for the same pair.  total = offsets[N]; idx
+ * holds total entries.  A point index outside [0, Np) gives NaN in its row.
+ * total == 0 is a no-op.  EINVAL as gcdf_eval_grad, or Np > 2^31 - 1, c NULL,
+ * total < 0. */
+gcdf_status gcdf_eval_grad_csr(gcdf_ctx* ctx, const float* knots, int64_t N, const float* points, int64_t Np,
+                               const int64_t* offsets, const int32_t* idx, int64_t total, float* c, float* J,
+                               void* stream);
+
+/* Sparsity pattern of the (total) x (col0 + N*state_dim) constraint Jacobian
+ * in CSR form whose values array is J of gcdf_eval_grad_csr as it stands:
+ * row_ptr int64[total+1] with row_ptr[r] = 9r, and cols int32[9*total] with
+ * cols[9r + c] = col0 + state_dim*i + c for the knot i of row r (state_dim = 18
+ * for x_i = [q_i, v_i]).  EINVAL: NULL pointers, N <= 0, total < 0,
+ * state_dim < 9, col0 < 0 or col0 + state_dim*N > 2^31 - 1. */
+gcdf_status gcdf_jacobian_pattern(gcdf_ctx* ctx, const int64_t* offsets, int64_t N, int64_t total,
+                                  int32_t state_dim, int64_t col0, int64_t* row_ptr, int32_t* cols,
+                                  void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of trajectory-optimisation requests.         */
 /* ------------------------------------------------------------------------ */
 

@@ -78,6 +78,15 @@ def library() -> ctypes.CDLL:
     lib.gcdf_train_forward.restype = ctypes.c_int
     lib.gcdf_train_backward.argtypes = [P, P, P, P, I64, P, P, P]
     lib.gcdf_train_backward.restype = ctypes.c_int
+    F = ctypes.c_float
+    lib.gcdf_partition_count.argtypes = [P, P, I64, I64, P, I64, F, P, P]
+    lib.gcdf_partition_count.restype = ctypes.c_int
+    lib.gcdf_partition_fill.argtypes = [P, P, I64, I64, P, I64, F, P, P, I64, P]
+    lib.gcdf_partition_fill.restype = ctypes.c_int
+    lib.gcdf_eval_grad_csr.argtypes = [P, P, I64, P, I64, P, P, I64, P, P, P]
+    lib.gcdf_eval_grad_csr.restype = ctypes.c_int
+    lib.gcdf_jacobian_pattern.argtypes = [P, P, I64, I64, ctypes.c_int32, I64, P, P, P]
+    lib.gcdf_jacobian_pattern.restype = ctypes.c_int
     lib.gcdf_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.gcdf_submit.restype = ctypes.c_int
     lib.gcdf_poll.argtypes = [P, ctypes.c_uint64]
@@ -88,7 +97,8 @@ def library() -> ctypes.CDLL:
 
 EXPORTED = ["gcdf_create", "gcdf_destroy", "gcdf_last_error", "gcdf_eval", "gcdf_eval_grad",
             "gcdf_knot_min", "gcdf_query", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
-            "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward"]
+            "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward",
+            "gcdf_partition_count", "gcdf_partition_fill", "gcdf_eval_grad_csr", "gcdf_jacobian_pattern"]
 
 
 def _check(st: int, ctx=None):
@@ -205,6 +215,56 @@ class Context:
         _check(library().gcdf_query(self._h, _ptr(knots), K, _ptr(points), Np, _ptr(d), _ptr(J), _ptr(dmin),
                                     _ptr(argmin), _ptr(Jmin), _stream(stream)), self._h)
         return d, J, dmin, argmin, Jmin
+
+    # -- obstacle partitions and the sparse constraint Jacobian --------------
+    def partition(self, ref, points, radius: float, ref_stride: int | None = None, stream=None):
+        """CSR partitions (offsets int64[N+1], idx int32[total]) of the points
+        around each reference base position (rows of ``ref``; its first two
+        columns are (x, y)).  Synchronises once to size idx."""
+        import torch
+
+        if ref.dtype != torch.float32 or not ref.is_cuda or not ref.is_contiguous() or ref.dim() != 2:
+            raise ValueError("ref must be a contiguous 2-D float32 CUDA tensor")
+        N, Np = ref.shape[0], points.shape[0]
+        _need(points, (Np, 3), "points")
+        stride = ref.shape[1] if ref_stride is None else ref_stride
+        off = torch.empty(N + 1, dtype=torch.int64, device=ref.device)
+        lib = library()
+        _check(lib.gcdf_partition_count(self._h, _ptr(ref), N, stride, _ptr(points), Np, float(radius), _ptr(off),
+                                        _stream(stream)), self._h)
+        total = int(off[-1].item())
+        idx = torch.empty(max(total, 1), dtype=torch.int32, device=ref.device)
+        _check(lib.gcdf_partition_fill(self._h, _ptr(ref), N, stride, _ptr(points), Np, float(radius), _ptr(off),
+                                       _ptr(idx), total, _stream(stream)), self._h)
+        return off, idx[:total]
+
+    def eval_grad_csr(self, knots, points, offsets, idx, with_grad: bool = True, c=None, J=None, stream=None):
+        """Stacked constraints c (float32[total]) and gradient rows J (float32[total][9])."""
+        import torch
+
+        N, Np, total = knots.shape[0], points.shape[0], idx.shape[0]
+        _need(knots, (N, 9), "knots")
+        _need(points, (Np, 3), "points")
+        if offsets.dtype != torch.int64 or idx.dtype != torch.int32 or offsets.shape[0] != N + 1:
+            raise ValueError("offsets must be int64[N+1] and idx int32[total]")
+        if c is None:
+            c = torch.empty(total, dtype=torch.float32, device=knots.device)
+        if with_grad and J is None:
+            J = torch.empty((total, 9), dtype=torch.float32, device=knots.device)
+        _check(library().gcdf_eval_grad_csr(self._h, _ptr(knots), N, _ptr(points), Np, _ptr(offsets), _ptr(idx),
+                                            total, _ptr(c), _ptr(J) if with_grad else None, _stream(stream)), self._h)
+        return (c, J) if with_grad else c
+
+    def jacobian_pattern(self, offsets, total: int, state_dim: int = 18, col0: int = 0, stream=None):
+        """CSR pattern (row_ptr int64[total+1], cols int32[9 total]) whose values are J rows."""
+        import torch
+
+        N = offsets.shape[0] - 1
+        row_ptr = torch.empty(total + 1, dtype=torch.int64, device=offsets.device)
+        cols = torch.empty(max(9 * total, 1), dtype=torch.int32, device=offsets.device)
+        _check(library().gcdf_jacobian_pattern(self._h, _ptr(offsets), N, total, state_dim, col0, _ptr(row_ptr),
+                                               _ptr(cols), _stream(stream)), self._h)
+        return row_ptr, cols[:9 * total]
 
     # -- serving ------------------------------------------------------------
     def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None) -> int:

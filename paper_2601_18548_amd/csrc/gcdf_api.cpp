@@ -269,6 +269,79 @@ gcdf_status gcdf_knot_min(gcdf_ctx* ctx, const float* knots, int64_t K, const fl
   return gcdf_query(ctx, knots, K, points, Np, nullptr, nullptr, dmin, argmin, Jmin, stream);
 }
 
+gcdf_status gcdf_partition_count(gcdf_ctx* ctx, const float* ref, int64_t N, int64_t ref_stride, const float* points,
+                                 int64_t Np, float radius, int64_t* offsets, void* stream) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!ref || !points || !offsets) return fail(GCDF_EINVAL, "ref/points/offsets pointer is NULL");
+  if (N <= 0 || Np <= 0) return fail(GCDF_EINVAL, "N and Np must be positive (N=%lld, Np=%lld)", (long long)N, (long long)Np);
+  if (Np > INT32_MAX) return fail(GCDF_EINVAL, "Np=%lld exceeds 2^31-1", (long long)Np);
+  if (ref_stride < 2) return fail(GCDF_EINVAL, "ref_stride must be >= 2 (got %lld)", (long long)ref_stride);
+  if (!(radius >= 0.f) || radius > 3.0e38f) return fail(GCDF_EINVAL, "radius must be finite and >= 0");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = gcdf::launch_partition_count(ref, N, ref_stride, points, Np, radius, offsets,
+                                              static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_partition_count launch");
+}
+
+gcdf_status gcdf_partition_fill(gcdf_ctx* ctx, const float* ref, int64_t N, int64_t ref_stride, const float* points,
+                                int64_t Np, float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
+                                void* stream) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!ref || !points || !offsets) return fail(GCDF_EINVAL, "ref/points/offsets pointer is NULL");
+  if (N <= 0 || Np <= 0) return fail(GCDF_EINVAL, "N and Np must be positive (N=%lld, Np=%lld)", (long long)N, (long long)Np);
+  if (Np > INT32_MAX) return fail(GCDF_EINVAL, "Np=%lld exceeds 2^31-1", (long long)Np);
+  if (ref_stride < 2) return fail(GCDF_EINVAL, "ref_stride must be >= 2 (got %lld)", (long long)ref_stride);
+  if (!(radius >= 0.f) || radius > 3.0e38f) return fail(GCDF_EINVAL, "radius must be finite and >= 0");
+  if (capacity < 0 || (capacity > 0 && !idx)) return fail(GCDF_EINVAL, "idx is NULL or capacity < 0");
+  if (capacity == 0) return GCDF_OK;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = gcdf::launch_partition_fill(ref, N, ref_stride, points, Np, radius, offsets, idx, capacity,
+                                             static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_partition_fill launch");
+}
+
+gcdf_status gcdf_eval_grad_csr(gcdf_ctx* ctx, const float* knots, int64_t N, const float* points, int64_t Np,
+                               const int64_t* offsets, const int32_t* idx, int64_t total, float* c, float* J,
+                               void* stream) {
+  gcdf_status st = check_query(ctx, knots, N, points, Np);
+  if (st != GCDF_OK) return st;
+  if (Np > INT32_MAX) return fail(GCDF_EINVAL, "Np=%lld exceeds 2^31-1", (long long)Np);
+  if (total < 0) return fail(GCDF_EINVAL, "total must be >= 0");
+  if (total > INT64_MAX / 9) return fail(GCDF_EINVAL, "total*9 overflows int64");
+  if (!c) return fail(GCDF_EINVAL, "c is NULL");
+  if (total == 0) return GCDF_OK;
+  if (!offsets || !idx) return fail(GCDF_EINVAL, "offsets/idx pointer is NULL");
+  DeviceGuard guard(ctx->device);
+  gcdf::Job job{};
+  job.knots = knots;
+  job.points = points;
+  job.K = N;
+  job.Np = Np;
+  job.csr_off = offsets;
+  job.csr_n = N;
+  job.csr_idx = idx;
+  job.npairs = total;
+  job.d = c;
+  job.J = J;
+  hipError_t e = gcdf::launch_fused(ctx->net, job, true, J != nullptr, ctx->num_cu, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_eval_grad_csr launch");
+}
+
+gcdf_status gcdf_jacobian_pattern(gcdf_ctx* ctx, const int64_t* offsets, int64_t N, int64_t total, int32_t state_dim,
+                                  int64_t col0, int64_t* row_ptr, int32_t* cols, void* stream) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!offsets || !row_ptr || (total > 0 && !cols)) return fail(GCDF_EINVAL, "offsets/row_ptr/cols pointer is NULL");
+  if (N <= 0 || total < 0) return fail(GCDF_EINVAL, "N must be positive and total >= 0");
+  if (state_dim < 9) return fail(GCDF_EINVAL, "state_dim must be >= 9 (got %d)", state_dim);
+  if (col0 < 0 || col0 > INT32_MAX - (int64_t)state_dim * N)
+    return fail(GCDF_EINVAL, "columns col0 + state_dim*N exceed 2^31-1");
+  if (total >= ((int64_t)1 << 38)) return fail(GCDF_EINVAL, "total=%lld too large", (long long)total);
+  DeviceGuard guard(ctx->device);
+  hipError_t e = gcdf::launch_jacobian_pattern(offsets, N, total, state_dim, col0, row_ptr, cols,
+                                               static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_jacobian_pattern launch");
+}
+
 gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return fail(GCDF_EINVAL, "NULL argument to gcdf_submit");
   if (!ctx->server) return fail(GCDF_EINVAL, "serving is disabled (serve_mem_budget == 0)");

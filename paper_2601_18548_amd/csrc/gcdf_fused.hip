@@ -649,21 +649,40 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     const int64_t qc = q < qlimit ? q : qlimit - 1;   // clamp the ragged tail (never stored)
     int64_t ki, pi;
     if constexpr (PAIRS) {
-      ki = job.kidx ? job.kidx[qc] : qc;
-      pi = job.pidx ? job.pidx[qc] : qc;
+      if (job.csr_off) {
+        // knot of row qc: the last i < csr_n with csr_off[i] <= qc (empty partitions skipped)
+        int64_t lo = 0, hi = job.csr_n - 1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) >> 1;
+          if (job.csr_off[mid] <= qc) lo = mid; else hi = mid - 1;
+        }
+        ki = lo;
+        pi = job.csr_idx[qc];
+      } else {
+        ki = job.kidx ? job.kidx[qc] : qc;
+        pi = job.pidx ? job.pidx[qc] : qc;
+      }
     } else {
       ki = kk;
       pi = qc;
     }
     const float* kn = job.knots + ki * kInDim;
-    const float* pt = job.points + pi * 3;
+    float pxyz[3];
+    if (PAIRS && (uint64_t)pi >= (uint64_t)job.Np) {
+      pxyz[0] = pxyz[1] = pxyz[2] = __builtin_nanf("");  // bad point index: NaN results
+    } else {
+      const float* pt = job.points + pi * 3;
+      pxyz[0] = pt[0];
+      pxyz[1] = pt[1];
+      pxyz[2] = pt[2];
+    }
     float sn, cs;
     sincosf(kn[2], &sn, &cs);
-    const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
+    const float ux = pxyz[0] - kn[0], uy = pxyz[1] - kn[1];
     float* x = xin + tid * XF;
     x[0] = cs * ux + sn * uy;
     x[1] = -sn * ux + cs * uy;
-    x[2] = pt[2];
+    x[2] = pxyz[2];
     x[3] = cs;
     x[4] = sn;
 #pragma unroll

@@ -36,6 +36,12 @@ struct Job {
   const int64_t* kidx;
   const int64_t* pidx;
   int64_t npairs;
+  // CSR pairs (pairs mode, when csr_off is set): pair r belongs to the knot i with
+  // csr_off[i] <= r < csr_off[i+1] (i < csr_n) and to point csr_idx[r]; a point index
+  // outside [0, Np) yields NaN outputs for that pair.
+  const int64_t* csr_off;
+  int64_t csr_n;
+  const int32_t* csr_idx;
   float* d;                  // dense: [K][Np]; pairs: [npairs]      (nullable)
   float* J;                  // dense: [K][Np][9]; pairs: [npairs][9] (nullable)
   unsigned long long* minkey;// dense only: [K] ordered (distance, index) keys (nullable)
@@ -62,6 +68,20 @@ hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int wi
 
 // Reorder nvec consecutive row vectors of length width into lane-major row order.
 hipError_t pack_row_vectors(const float* src, float* dst, int width, int nvec, hipStream_t s);
+
+// Obstacle partitions: offsets[i+1] - offsets[i] = number of points within `radius`
+// (planar distance) of reference base position i (ref + i * ref_stride), offsets[0] = 0.
+hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
+                                  float radius, int64_t* offsets, hipStream_t s);
+// idx[offsets[i] + k] = k-th point (ascending) of partition i; entries at positions >=
+// capacity are not written.
+hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
+                                 float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
+                                 hipStream_t s);
+// Sparsity pattern of the stacked constraint Jacobian: row_ptr[r] = n_conf * r (r <= total),
+// cols[n_conf * r + c] = col0 + state_dim * knot(r) + c.
+hipError_t launch_jacobian_pattern(const int64_t* offsets, int64_t N, int64_t total, int32_t state_dim, int64_t col0,
+                                   int64_t* row_ptr, int32_t* cols, hipStream_t s);
 
 // Launch the fused query kernel (dense all-pairs if !pairs, else the pair list).
 hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s);

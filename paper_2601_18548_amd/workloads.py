@@ -11,7 +11,7 @@ translation (x, y), the base yaw (first rotational coordinate), then the six
 arm joints -> ``float32[K][9]`` in the order (x, y, yaw, a1..a6).
 
 Obstacle points are stored as ``float32[Np][3]`` world coordinates, the "one
-array of all obstacle coordinates" of the partition data structure (Sec. IV-B).
+array of all obstacle coordinates" of the partition data structure (Sec. IV-A).
 
 All generators use numpy's PCG64 with an explicit seed.
 """
@@ -47,6 +47,22 @@ def knots(K: int, seed: int) -> np.ndarray:
     yaw = r.uniform(-math.pi, math.pi, size=(K, 1))
     arm = r.uniform(-math.pi, math.pi, size=(K, 6))
     return np.ascontiguousarray(np.concatenate([xy, yaw, arm], axis=1), dtype=np.float32)
+
+
+def trajectory(N: int, seed: int) -> np.ndarray:
+    """N knots along one planar base path across the workspace box: the base
+    moves from x = -2.5 to 2.5 with a sinusoidal y offset, yaw along the path
+    tangent, arm joints a smooth random walk.  ``float32[N][9]``; consecutive
+    knots are close, so their obstacle partitions overlap."""
+    r = _rng(seed)
+    s = np.linspace(0.0, 1.0, N)
+    amp, phase = r.uniform(0.5, 1.5), r.uniform(-math.pi, math.pi)
+    x = -2.5 + 5.0 * s
+    y = amp * np.sin(2 * math.pi * s + phase)
+    dy = amp * 2 * math.pi * np.cos(2 * math.pi * s + phase) / 5.0
+    yaw = np.arctan2(dy, np.ones_like(dy))
+    arm = np.cumsum(r.normal(0.0, 0.1, size=(N, 6)), axis=0) + r.uniform(-1.0, 1.0, size=6)
+    return np.concatenate([x[:, None], y[:, None], yaw[:, None], arm], axis=1).astype(np.float32)
 
 
 def points_uniform(Np: int, seed: int) -> np.ndarray:
