@@ -180,6 +180,26 @@ gcdf_status gcdf_jacobian_pattern(gcdf_ctx* ctx, const int64_t* offsets, int64_t
                                   int32_t state_dim, int64_t col0, int64_t* row_ptr, int32_t* cols,
                                   void* stream);
 
+/* Single-step projection onto the zero set and the weighted eikonal norm
+ * (Theorem 1): for a pair with distance f and configuration gradient J,
+ *   qz = q - f * M^{-1} J,    eik = |J|_{M^{-1}} = sqrt(sum_c J_c^2 / m_c),
+ * with q the pair's knot and M = diag(m_diag), m_diag a HOST float[9] of finite
+ * positive weights (for a true GCDF, eik = 1 and qz lies on the zero set).
+ * Rows follow gcdf_eval_grad's layout: d float32[K][Np], J float32[K][Np][9],
+ * qz float32[K][Np][9], eik float32[K][Np]; either output may be NULL (not
+ * both).  Computed in float32 (q_c - f * (J_c * (1/m_c))).  EINVAL: NULL
+ * inputs, no output, K or Np <= 0, a weight not finite and positive. */
+gcdf_status gcdf_project(gcdf_ctx* ctx, const float* knots, int64_t K, int64_t Np, const float* d,
+                         const float* J, const float* m_diag, float* qz, float* eik, void* stream);
+
+/* The same over the stacked CSR rows of gcdf_eval_grad_csr (c float32[total],
+ * J float32[total][9], qz float32[total][9], eik float32[total]); row r uses
+ * the knot of its partition.  Bitwise equal to gcdf_project's entries for the
+ * same pairs.  total == 0 is a no-op. */
+gcdf_status gcdf_project_csr(gcdf_ctx* ctx, const float* knots, int64_t N, const int64_t* offsets,
+                             int64_t total, const float* c, const float* J, const float* m_diag, float* qz,
+                             float* eik, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of trajectory-optimisation requests.         */
 /* ------------------------------------------------------------------------ */

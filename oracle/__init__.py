@@ -159,6 +159,20 @@ def eval_pairs(blob: bytes, knots, points, kidx, pidx, with_grad: bool = True, n
     return d, J
 
 
+def project(q, f, J, m_diag):
+    """Single-step projection onto the zero set and the weighted eikonal norm
+    (Theorem 1): q_z = q - f M^{-1} grad_q f and |grad_q f|_{M^{-1}}, with
+    M = diag(m_diag) positive.  q (..., 9), f (...), J (..., 9) broadcast
+    together; float64 results (q_z (..., 9), eik (...))."""
+    q = np.asarray(q, np.float64)
+    f = np.asarray(f, np.float64)
+    J = np.asarray(J, np.float64)
+    minv = 1.0 / np.asarray(m_diag, np.float64)
+    qz = q - f[..., None] * (minv * J)
+    eik = np.sqrt(np.sum(minv * J * J, axis=-1))
+    return qz, eik
+
+
 def knot_min(d):
     """Per-row minimum of d (K, Np) and the lowest column index attaining it."""
     d = np.ascontiguousarray(d, dtype=np.float64)

@@ -87,6 +87,10 @@ def library() -> ctypes.CDLL:
     lib.gcdf_eval_grad_csr.restype = ctypes.c_int
     lib.gcdf_jacobian_pattern.argtypes = [P, P, I64, I64, ctypes.c_int32, I64, P, P, P]
     lib.gcdf_jacobian_pattern.restype = ctypes.c_int
+    lib.gcdf_project.argtypes = [P, P, I64, I64, P, P, P, P, P, P]
+    lib.gcdf_project.restype = ctypes.c_int
+    lib.gcdf_project_csr.argtypes = [P, P, I64, P, I64, P, P, P, P, P, P]
+    lib.gcdf_project_csr.restype = ctypes.c_int
     lib.gcdf_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
     lib.gcdf_submit.restype = ctypes.c_int
     lib.gcdf_poll.argtypes = [P, ctypes.c_uint64]
@@ -98,7 +102,8 @@ def library() -> ctypes.CDLL:
 EXPORTED = ["gcdf_create", "gcdf_destroy", "gcdf_last_error", "gcdf_eval", "gcdf_eval_grad",
             "gcdf_knot_min", "gcdf_query", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
             "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward",
-            "gcdf_partition_count", "gcdf_partition_fill", "gcdf_eval_grad_csr", "gcdf_jacobian_pattern"]
+            "gcdf_partition_count", "gcdf_partition_fill", "gcdf_eval_grad_csr", "gcdf_jacobian_pattern",
+            "gcdf_project", "gcdf_project_csr"]
 
 
 def _check(st: int, ctx=None):
@@ -265,6 +270,33 @@ class Context:
         _check(library().gcdf_jacobian_pattern(self._h, _ptr(offsets), N, total, state_dim, col0, _ptr(row_ptr),
                                                _ptr(cols), _stream(stream)), self._h)
         return row_ptr, cols[:9 * total]
+
+    def project(self, knots, d, J, m_diag, offsets=None, with_qz: bool = True, with_eik: bool = True, stream=None):
+        """Theorem 1 projection: (qz, eik) for dense rows (d (K, Np), J (K, Np, 9))
+        or, with ``offsets``, the stacked CSR rows (c (total,), J (total, 9))."""
+        import torch
+
+        m = (ctypes.c_float * 9)(*[float(v) for v in m_diag])
+        N = knots.shape[0]
+        _need(knots, (N, 9), "knots")
+        shape = tuple(d.shape)
+        _need(d, shape, "d")
+        _need(J, shape + (9,), "J")
+        qz = torch.empty(shape + (9,), dtype=torch.float32, device=d.device) if with_qz else None
+        eik = torch.empty(shape, dtype=torch.float32, device=d.device) if with_eik else None
+        lib = library()
+        if offsets is None:
+            if len(shape) != 2 or shape[0] != N:
+                raise ValueError("dense d must be (K, Np)")
+            st = lib.gcdf_project(self._h, _ptr(knots), N, shape[1], _ptr(d), _ptr(J), m, _ptr(qz), _ptr(eik),
+                                  _stream(stream))
+        else:
+            if len(shape) != 1 or offsets.dtype != torch.int64 or offsets.shape[0] != N + 1:
+                raise ValueError("CSR c must be (total,) with offsets int64[N+1]")
+            st = lib.gcdf_project_csr(self._h, _ptr(knots), N, _ptr(offsets), shape[0], _ptr(d), _ptr(J), m,
+                                      _ptr(qz), _ptr(eik), _stream(stream))
+        _check(st, self._h)
+        return qz, eik
 
     # -- serving ------------------------------------------------------------
     def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None) -> int:

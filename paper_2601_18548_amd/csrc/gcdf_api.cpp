@@ -342,6 +342,43 @@ gcdf_status gcdf_jacobian_pattern(gcdf_ctx* ctx, const int64_t* offsets, int64_t
   return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_jacobian_pattern launch");
 }
 
+namespace {
+gcdf_status project_common(gcdf_ctx* ctx, const float* knots, int64_t N, int64_t Np, const int64_t* offsets,
+                           int64_t rows, const float* f, const float* J, const float* m_diag, float* qz, float* eik,
+                           void* stream) {
+  if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (!knots || !f || !J || !m_diag) return fail(GCDF_EINVAL, "knots/f/J/m_diag pointer is NULL");
+  if (!qz && !eik) return fail(GCDF_EINVAL, "no output requested");
+  gcdf::Minv9 minv{};
+  for (int c = 0; c < 9; ++c) {
+    if (!(m_diag[c] > 0.f) || m_diag[c] > 3.0e38f) return fail(GCDF_EINVAL, "m_diag[%d] must be finite and > 0", c);
+    minv.v[c] = 1.0f / m_diag[c];
+  }
+  if (rows == 0) return GCDF_OK;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = gcdf::launch_project(knots, N, Np, offsets, rows, f, J, minv, qz, eik,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_project launch");
+}
+}  // namespace
+
+gcdf_status gcdf_project(gcdf_ctx* ctx, const float* knots, int64_t K, int64_t Np, const float* d, const float* J,
+                         const float* m_diag, float* qz, float* eik, void* stream) {
+  if (K <= 0 || Np <= 0) return fail(GCDF_EINVAL, "K and Np must be positive (K=%lld, Np=%lld)", (long long)K, (long long)Np);
+  if (K > INT64_MAX / 9 / Np) return fail(GCDF_EINVAL, "K*Np*9 overflows int64");
+  if (K * Np >= ((int64_t)1 << 38)) return fail(GCDF_EINVAL, "K*Np too large");
+  return project_common(ctx, knots, K, Np, nullptr, K * Np, d, J, m_diag, qz, eik, stream);
+}
+
+gcdf_status gcdf_project_csr(gcdf_ctx* ctx, const float* knots, int64_t N, const int64_t* offsets, int64_t total,
+                             const float* c, const float* J, const float* m_diag, float* qz, float* eik,
+                             void* stream) {
+  if (N <= 0 || total < 0) return fail(GCDF_EINVAL, "N must be positive and total >= 0");
+  if (total >= ((int64_t)1 << 38)) return fail(GCDF_EINVAL, "total=%lld too large", (long long)total);
+  if (total > 0 && !offsets) return fail(GCDF_EINVAL, "offsets is NULL");
+  return project_common(ctx, knots, N, 1, offsets, total, c, J, m_diag, qz, eik, stream);
+}
+
 gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return fail(GCDF_EINVAL, "NULL argument to gcdf_submit");
   if (!ctx->server) return fail(GCDF_EINVAL, "serving is disabled (serve_mem_budget == 0)");

@@ -1,8 +1,9 @@
-// Obstacle partitions and the sparsity pattern of the stacked GCDF constraint
-// Jacobian (Sec. IV-A of the paper: partitions I_{M,i} of the obstacle points by
-// reference base position, the knot-major constraint vector c_gcdf, and the
-// projections P_i of each knot's dense gradient rows into the (sum m_i) x 2Nn
-// Jacobian).
+// What the solver needs around the query: obstacle partitions and the sparsity
+// pattern of the stacked GCDF constraint Jacobian (Sec. IV-A of the paper:
+// partitions I_{M,i} of the obstacle points by reference base position, the
+// knot-major constraint vector c_gcdf, and the projections P_i of each knot's
+// dense gradient rows into the (sum m_i) x 2Nn Jacobian), and the single-step
+// projection onto the zero set with the weighted eikonal norm (Theorem 1).
 //
 // Membership: point j is in partition i when its planar distance to reference
 // base position i is within the radius, decided in float32 as
@@ -160,7 +161,76 @@ __global__ void jacobian_pattern_kernel(const int64_t* __restrict__ offsets, int
   for (int c = 0; c < kInDim; ++c) cols[kInDim * r + c] = c0 + c;
 }
 
+// Knot of stacked row r: dense rows are knot-major with Np points per knot; CSR
+// rows take the last i < N with offsets[i] <= r.
+__device__ __forceinline__ int64_t row_knot(const int64_t* __restrict__ offsets, int64_t N, int64_t Np, int64_t r) {
+  if (!offsets) return r / Np;
+  int64_t lo = 0, hi = N - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Theorem 1: q_z = q - f M^{-1} J and |J|_{M^{-1}} per row.  A block stages its
+// 256 rows of J (9 floats each) through LDS so that the global loads and the q_z
+// stores are contiguous dword accesses; the kernel is bound by HBM (80 B per row).
+__global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ knots, int64_t N, int64_t Np,
+                                                      const int64_t* __restrict__ offsets, int64_t rows,
+                                                      const float* __restrict__ f, const float* __restrict__ J,
+                                                      Minv9 minv, float* __restrict__ qz, float* __restrict__ eik) {
+  constexpr int R = 256;
+  __shared__ float tile[R * kInDim];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int n = rows - r0 < R ? (int)(rows - r0) : R;
+  const int lim = n * kInDim;
+  const float* Jb = J + r0 * kInDim;
+#pragma unroll
+  for (int u = 0; u < kInDim; ++u) {
+    const int t = u * R + threadIdx.x;
+    tile[t] = t < lim ? Jb[t] : 0.f;
+  }
+  __syncthreads();
+  float out[kInDim];
+  const int me = threadIdx.x;
+  if (me < n) {
+    const int64_t r = r0 + me;
+    const float* kn = knots + row_knot(offsets, N, Np, r) * kInDim;
+    const float fr = f[r];
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < kInDim; ++c) {
+      const float j = tile[me * kInDim + c];
+      const float t = j * minv.v[c];
+      out[c] = kn[c] - fr * t;
+      s += t * j;
+    }
+    if (eik) eik[r] = sqrtf(s);
+  }
+  if (!qz) return;
+  __syncthreads();
+  if (me < n) {
+#pragma unroll
+    for (int c = 0; c < kInDim; ++c) tile[me * kInDim + c] = out[c];
+  }
+  __syncthreads();
+  float* Qb = qz + r0 * kInDim;
+#pragma unroll
+  for (int u = 0; u < kInDim; ++u) {
+    const int t = u * R + threadIdx.x;
+    if (t < lim) Qb[t] = tile[t];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_project(const float* knots, int64_t N, int64_t Np, const int64_t* offsets, int64_t rows,
+                          const float* f, const float* J, const Minv9& minv, float* qz, float* eik, hipStream_t s) {
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, knots, N, Np, offsets,
+                     rows, f, J, minv, qz, eik);
+  return hipGetLastError();
+}
 
 hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
                                   float radius, int64_t* offsets, hipStream_t s) {

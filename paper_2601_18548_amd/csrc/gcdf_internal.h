@@ -83,6 +83,16 @@ hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride
 hipError_t launch_jacobian_pattern(const int64_t* offsets, int64_t N, int64_t total, int32_t state_dim, int64_t col0,
                                    int64_t* row_ptr, int32_t* cols, hipStream_t s);
 
+// Single-step projection (Theorem 1) over stacked rows r < rows: the knot of row r
+// is r / Np (offsets == NULL, dense knot-major rows) or the CSR row's knot;
+// qz[r] = knot - f[r] * minv .* J[r] and eik[r] = sqrt(sum_c minv_c J[r][c]^2)
+// (either output may be NULL).
+struct Minv9 {
+  float v[kInDim];
+};
+hipError_t launch_project(const float* knots, int64_t N, int64_t Np, const int64_t* offsets, int64_t rows,
+                          const float* f, const float* J, const Minv9& minv, float* qz, float* eik, hipStream_t s);
+
 // Launch the fused query kernel (dense all-pairs if !pairs, else the pair list).
 hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s);
 

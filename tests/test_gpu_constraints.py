@@ -163,3 +163,78 @@ def test_argument_errors(gcdf, weights):
                                   None) == gcdf.OK
     assert lib.gcdf_eval_grad_csr(ctx._h, k.data_ptr(), 4, p.data_ptr(), 64, off.data_ptr(), None, 3, c.data_ptr(),
                                   None, None) == gcdf.EINVAL
+
+
+M_DIAG = [2.0, 2.0, 0.5, 1.0, 1.5, 1.0, 1.0, 3.0, 1.0]
+
+
+@pytest.mark.parametrize("precision", ["bf16x2", "fp32"])
+def test_projection_matches_oracle(gcdf, oracle_mod, weights, precision):
+    K, Np = 16, 700  # 11,200 rows: a ragged last block
+    k, p = wl.knots(K, 20), wl.points_patches(Np, 21)
+    ctx = gcdf.Context(weights.to_blob(), 256, precision)
+    kt, pt = cu(k), cu(p)
+    d, J = ctx.eval_grad(kt, pt)
+    qz, eik = ctx.project(kt, d, J, M_DIAG)
+    torch.cuda.synchronize()
+    dn, Jn, qn, en = d.cpu().numpy(), J.cpu().numpy(), qz.cpu().numpy(), eik.cpu().numpy()
+    # the kernel on its own inputs: the FP64 formula, float32 rounding only
+    qr, er = oracle_mod.project(k[:, None, :], dn, Jn, M_DIAG)
+    scale = 1.0 + np.abs(k[:, None, :]) + np.abs(dn[..., None] * Jn / np.asarray(M_DIAG))
+    assert np.all(np.abs(qn - qr) <= 4e-7 * scale)
+    assert np.all(np.abs(en - er) <= 4e-7 * er + 1e-30)
+    # end to end against the oracle's distances and gradients, on a sample
+    ki = np.arange(K).repeat(10)
+    pi = np.random.default_rng(22).integers(0, Np, len(ki))
+    d0, J0 = oracle_mod.eval_pairs(weights.to_blob(), k, p, ki, pi)
+    q0, e0 = oracle_mod.project(k[ki], d0, J0, M_DIAG)
+    tol_d, tol_j = (1e-3, 1e-2) if precision == "bf16x2" else (5e-5, 5e-5)
+    # |dqz| <= |dd| |M^-1 J| + |d| max(M^-1) |dJ| and |deik| <= sqrt(max(M^-1)) |dJ|,
+    # with |dd| <= tol_d and |dJ| <= tol_j max(|J|, 1e-3 median |J|) (the query's bar)
+    minv = 1.0 / np.asarray(M_DIAG)
+    nj = np.linalg.norm(J0, axis=1)
+    dj = tol_j * np.maximum(nj, 1e-3 * np.median(nj))
+    bound_q = tol_d * np.linalg.norm(minv * J0, axis=1) + np.abs(d0) * minv.max() * dj + 1e-5
+    assert np.all(np.linalg.norm(qn[ki, pi] - q0, axis=1) <= bound_q)
+    assert np.all(np.abs(en[ki, pi] - e0) <= np.sqrt(minv.max()) * dj + 1e-6)
+    # single outputs give the same values
+    q_only, _ = ctx.project(kt, d, J, M_DIAG, with_eik=False)
+    _, e_only = ctx.project(kt, d, J, M_DIAG, with_qz=False)
+    assert torch.equal(q_only, qz) and torch.equal(e_only, eik)
+
+
+def test_projection_csr_equals_dense(gcdf, cons, weights):
+    k = wl.trajectory(20, 23)
+    k[7, :2] += 50.0
+    p = wl.points_patches(2500, 24)
+    ctx = gcdf.Context(weights.to_blob(), 256, "bf16x2")
+    kt, pt = cu(k), cu(p)
+    off, idx = ctx.partition(kt, pt, 1.2, ref_stride=9)
+    c, J = ctx.eval_grad_csr(kt, pt, off, idx)
+    qz, eik = ctx.project(kt, c, J, M_DIAG, offsets=off)
+    d, Jd = ctx.eval_grad(kt, pt)
+    qd, ed = ctx.project(kt, d, Jd, M_DIAG)
+    torch.cuda.synchronize()
+    rows = cons.row_knots(off.cpu().numpy())
+    ix = idx.cpu().numpy().astype(np.int64)
+    assert np.array_equal(qz.cpu().numpy(), qd.cpu().numpy()[rows, ix])
+    assert np.array_equal(eik.cpu().numpy(), ed.cpu().numpy()[rows, ix])
+
+
+def test_projection_argument_errors(gcdf, weights):
+    ctx = gcdf.Context(weights.to_blob(), 256, "bf16x2")
+    lib = gcdf.library()
+    import ctypes
+
+    k = cu(wl.knots(2, 25))
+    d = torch.zeros((2, 3), device="cuda")
+    J = torch.zeros((2, 3, 9), device="cuda")
+    out = torch.empty((2, 3, 9), device="cuda")
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        m = (ctypes.c_float * 9)(*([1.0] * 8 + [bad]))
+        assert lib.gcdf_project(ctx._h, k.data_ptr(), 2, 3, d.data_ptr(), J.data_ptr(), m, out.data_ptr(), None,
+                                None) == gcdf.EINVAL
+    m = (ctypes.c_float * 9)(*([1.0] * 9))
+    assert lib.gcdf_project(ctx._h, k.data_ptr(), 2, 3, d.data_ptr(), J.data_ptr(), m, None, None, None) == gcdf.EINVAL
+    assert lib.gcdf_project(ctx._h, k.data_ptr(), 0, 3, d.data_ptr(), J.data_ptr(), m, out.data_ptr(), None,
+                            None) == gcdf.EINVAL

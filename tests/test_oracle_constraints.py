@@ -112,3 +112,23 @@ def test_constraint_vector_is_knot_major(cons, oracle_mod):
         sl = slice(off[i], off[i + 1])
         assert np.array_equal(c[sl], d[i, idx[sl]])
         assert np.array_equal(G[sl], J[i, idx[sl]])
+
+
+def test_projection_closed_form_weighted_plane(oracle_mod):
+    """Weighted distance to a hyperplane a.q = b: f = (a.q - b) / |a|_{M^-1}
+    (the M-norm distance), grad f = a / |a|_{M^-1}; one projection step lands
+    on the plane and the weighted eikonal norm is 1, for any diagonal M > 0."""
+    r = np.random.default_rng(4)
+    for _ in range(20):
+        a = r.normal(size=9)
+        b = r.normal()
+        m = r.uniform(0.2, 20.0, size=9)
+        q = r.normal(size=(5, 9))
+        na = np.sqrt(np.sum(a * a / m))
+        f = (q @ a - b) / na
+        J = np.tile(a / na, (5, 1))
+        qz, eik = oracle_mod.project(q, f, J, m)
+        np.testing.assert_allclose(qz @ a, b, atol=1e-12)
+        np.testing.assert_allclose(eik, 1.0, atol=1e-12)
+        # q_z is the M-closest point of the plane: |q - q_z|_M = |f|
+        np.testing.assert_allclose(np.sqrt(np.sum(m * (q - qz) ** 2, axis=1)), np.abs(f), rtol=1e-12)

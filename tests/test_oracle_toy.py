@@ -61,8 +61,13 @@ def test_weighted_eikonal_and_single_step_projection(oracle_mod, w_t):
             continue
         used += 1
         f = res["value"]
+        # the oracle's projection routine on the 9-coordinate layout (unused arm joints zero)
+        m9 = np.r_[w_t, w_t, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0]
+        qz9, eik = oracle_mod.project(_knot9(q)[0], f, np.r_[J, 0, 0, 0, 0], m9)
+        assert eik == pytest.approx(1.0, abs=1e-9)  # Theorem 1 (1)
+        qz = qz9[:5]  # Theorem 1 (2)
+        assert np.array_equal(qz9[5:], np.zeros(4))
         assert math.sqrt(np.sum(minv * J * J)) == pytest.approx(1.0, abs=1e-9)
-        qz = q - f * minv * J  # Theorem 1 (2)
         assert abs(toy.sdf_world(p, qz)) < 1e-8
         # the projected arm lands exactly on the grid minimiser
         np.testing.assert_allclose(toy.wrap(qz[3:5] - np.array(res["arm"])), 0.0, atol=1e-12)
