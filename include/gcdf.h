@@ -18,7 +18,7 @@
  *   4. reduce by minimum over the points of each knot.
  *
  * Results are knot-major as the constraint vector c_gcdf and its dense
- * gradient matrix are stacked (eq. cdf_constraints_vector, Sec. IV-B):
+ * gradient matrix are stacked (eq. cdf_constraints_vector, Sec. IV-A):
  *   d[i*Np + j]          distance for knot i, point j
  *   J[(i*Np + j)*9 + c]  d d / d q_i[c], c in (x, y, yaw, a1..a6)
  *

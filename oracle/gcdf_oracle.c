@@ -21,7 +21,7 @@
  *   - the derivative of d with respect to the full configuration, by the
  *     chain rule through the point coordinates (Sec. III-B), ordered
  *     (x, y, yaw, a1..a6): the gradient the constraint Jacobian stacks
- *     row by row (Sec. IV-B, dense gradient matrix).
+ *     row by row (Sec. IV-A, dense gradient matrix).
  *   - per knot, the minimum over points and the lowest index attaining it
  *     (the constraint f - delta >= 0 of eq. optimization-in-general holds
  *     for all points iff it holds for the minimum).

@@ -9,7 +9,7 @@
 //   -> stores of d / J -> per-knot minimum (64-bit ordered-key atomic min).
 // (Steps of the query: Sec. III-B base-frame transform and chain rule,
 // Sec. III-C network on [p', a], Sec. IV-A constraint over all knot/point
-// pairs, Sec. IV-B knot-major stacking.)
+// pairs, Sec. IV-A knot-major stacking.)
 //
 // Work split inside the tile: every hidden layer is C[W x 64] = M[W x W] B[W x 64]
 // with M = W_l (forward) or W_l^T (reverse) and B = the previous layer's
