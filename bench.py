@@ -14,6 +14,8 @@ Prints one JSON line: pairs (queries) per second, plus
   cpu_baseline : the FP64 CPU oracle on a bounded sample of the same pairs;
   modes        : the same workload in FP32 and pure BF16 (context, same metric);
   serving      : p50 / p99 latency of a Poisson request trace through gcdf_submit;
+  constraints  : partitions around a 128-knot trajectory, the CSR query, the
+                 Jacobian pattern and the single-step projection (HBM roofline);
   training     : steps/s of the width-256 training step (batch 65,536, Adam).
 """
 from __future__ import annotations
@@ -155,6 +157,63 @@ def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precis
             "overloaded": bool(n_requests / elapsed < 0.95 * rate_hz)}
 
 
+def _event_ms(torch, stream, fn, reps: int) -> float:
+    """Mean milliseconds of fn() on `stream`, from HIP events around each call."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / reps
+
+
+def constraints_bench(g, torch, wk, reps: int = 5, n_knots: int = 128, radius: float = 1.5):
+    """The solver-side calls on the benchmark cloud: partitions of the points around
+    a 128-knot trajectory, the CSR query over them (same network and precision as
+    the main workload), the Jacobian pattern, and the single-step projection over
+    the dense outputs of the main workload (an HBM-bound epilogue: 80 B per row)."""
+    from paper_2601_18548_amd import workloads as wl
+
+    ctx = g.Context(wk.weights.to_blob(), wk.width, wk.precision)
+    stream = torch.cuda.current_stream()
+    tr = torch.from_numpy(wl.trajectory(n_knots, 901)).cuda()
+    pt = torch.from_numpy(wk.points).cuda()
+    kt = torch.from_numpy(wk.knots).cuda()
+    out = {}
+    ctx.partition(tr, pt, radius, ref_stride=9)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        off, idx = ctx.partition(tr, pt, radius, ref_stride=9)
+    torch.cuda.synchronize()
+    total = int(idx.shape[0])
+    out["partition"] = {"knots": n_knots, "points": wk.Np, "radius_m": radius, "rows": total,
+                        "ms_per_build_incl_size_sync": (time.perf_counter() - t0) / reps * 1e3}
+    c = torch.empty(total, device="cuda")
+    J = torch.empty((total, 9), device="cuda")
+    ctx.eval_grad_csr(tr, pt, off, idx, c=c, J=J)
+    kms = _event_ms(torch, stream, lambda: ctx.eval_grad_csr(tr, pt, off, idx, c=c, J=J, stream=stream), reps)
+    fl = flops_per_pair(wk.width) * total
+    out["csr_query"] = {"rows": total, "kernel_ms": kms, "rows_per_s": total / (kms * 1e-3),
+                        "tflops": fl / (kms * 1e-3) / 1e12, "frac_of_peak": fl / (kms * 1e-3) / 1e12 / PEAK_TFLOPS[wk.precision]}
+    pms = _event_ms(torch, stream, lambda: ctx.jacobian_pattern(off, total, stream=stream), reps)
+    out["jacobian_pattern"] = {"rows": total, "ms": pms, "bytes": 44 * total, "gbps": 44 * total / (pms * 1e-3) / 1e9}
+    d = torch.empty((wk.K, wk.Np), device="cuda")
+    Jd = torch.empty((wk.K, wk.Np, 9), device="cuda")
+    ctx.eval_grad(kt, pt, d, Jd)
+    m = [2.0, 2.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0]
+    ctx.project(kt, d, Jd, m)
+    jms = _event_ms(torch, stream, lambda: ctx.project(kt, d, Jd, m, stream=stream), reps * 4)
+    rows = wk.K * wk.Np
+    gbps = 80.0 * rows / (jms * 1e-3) / 1e9
+    out["projection"] = {"rows": rows, "kernel_ms": jms, "algorithmic_bytes_per_row": 80, "gbps": gbps,
+                         "roofline": {"bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
+                                      "frac": gbps / 8000.0}}
+    ctx.close()
+    return out
+
+
 def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
     """Training step of the width-256 network: MSE against a seeded teacher's
     distances plus N(0, 1e-3) noise, hand-written forward/backward behind
@@ -222,6 +281,9 @@ def main():
     ap.add_argument("--no-modes", action="store_true", help="skip the FP32 / pure-BF16 context runs")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--no-constraints", action="store_true", help="skip the partition / CSR / projection leg")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     args = ap.parse_args()
@@ -231,6 +293,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "copies": 5}), flush=True)
+        return
 
     import paper_2601_18548_amd as g
     from paper_2601_18548_amd import workloads as wl
@@ -296,6 +368,9 @@ def main():
         out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests)
         print("bench: serving p50 %.1f ms p99 %.1f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]),
               file=sys.stderr, flush=True)
+    if not args.no_constraints and args.workload == "bf16":
+        out["constraints"] = constraints_bench(g, torch, wk)
+        print("bench: constraints %s" % json.dumps(out["constraints"]), file=sys.stderr, flush=True)
     if args.train_steps > 0:
         out["training"] = train_bench(torch, args.train_steps, 3)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)

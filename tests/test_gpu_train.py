@@ -1,9 +1,9 @@
 """Training form on the GPU: weight gradients vs the FP64 oracle, finite
 differences of the GPU loss, determinism, autograd + Adam.
 
-Tolerances: FP32 mode, per parameter array, |g - g_ref| / |g_ref| <= 1e-4
+Tolerances: FP32 mode, per parameter array, |g - g_ref| / |g_ref| <= 1e-5
 (FP32 accumulation over a few hundred samples); BF16 mode (activations and
-gradients rounded to BF16 for the matrix cores) <= 5e-2, printed.
+gradients rounded to BF16 for the matrix cores) <= 2e-2, printed.
 """
 import numpy as np
 import pytest
@@ -52,7 +52,7 @@ def split(flat, w):
     return out
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", 5e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
 def test_weight_gradients_match_oracle(tr_mod, oracle_mod, precision, tol):
     w = wl.weights(256, seed=31, bf16_hidden=False)  # FP32 master weights, off the BF16 grid
     k, p, y = batch(300, 3)  # ragged: not a multiple of 64
