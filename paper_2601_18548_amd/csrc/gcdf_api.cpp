@@ -43,6 +43,7 @@ struct gcdf_ctx {
   unsigned long long* minkey = nullptr;  // [max_knots]
   int64_t* pair_k = nullptr;          // [max_knots]
   int64_t* pair_p = nullptr;          // [max_knots]
+  int64_t* tile_off = nullptr;        // [max_knots + 1] (CSR query)
   gcdf::Server* server = nullptr;
 };
 
@@ -128,7 +129,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   const size_t off_b5 = align(off_w5 + (size_t)W * 4);
   const size_t off_m = align(off_b5 + 4);
   const size_t total = off_m + 6 * align(mbytes);
-  const size_t ws = (size_t)c->cfg.max_knots * (8 + 8 + 8);
+  const size_t ws = (size_t)c->cfg.max_knots * (8 + 8 + 8 + 8) + 8;
   float* staging = nullptr;
   e = hipMalloc(&c->wbuf, total);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->minkey), ws);
@@ -140,6 +141,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   }
   c->pair_k = reinterpret_cast<int64_t*>(c->minkey + c->cfg.max_knots);
   c->pair_p = c->pair_k + c->cfg.max_knots;
+  c->tile_off = c->pair_p + c->cfg.max_knots;
   hipStream_t s = nullptr;
   e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMemcpyAsync(staging, static_cast<const char*>(blob) + kHeader, 4 * nfloat, hipMemcpyHostToDevice, s);
@@ -311,19 +313,25 @@ gcdf_status gcdf_eval_grad_csr(gcdf_ctx* ctx, const float* knots, int64_t N, con
   if (!c) return fail(GCDF_EINVAL, "c is NULL");
   if (total == 0) return GCDF_OK;
   if (!offsets || !idx) return fail(GCDF_EINVAL, "offsets/idx pointer is NULL");
+  if (N > ctx->cfg.max_knots)
+    return fail(GCDF_EINVAL, "N=%lld exceeds max_knots=%lld", (long long)N, (long long)ctx->cfg.max_knots);
   DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // each knot's rows run as gathered dense tiles (one knot per tile): the arm term
+  // of the input layer is computed once per tile, as in the dense query
+  hipError_t e = gcdf::launch_csr_tile_offsets(offsets, N, ctx->tile_off, s);
   gcdf::Job job{};
   job.knots = knots;
   job.points = points;
   job.K = N;
   job.Np = Np;
-  job.csr_off = offsets;
-  job.csr_n = N;
-  job.csr_idx = idx;
-  job.npairs = total;
+  job.tile_off = ctx->tile_off;
+  job.row_off = offsets;
+  job.pgather = idx;
+  job.ntiles_bound = (total + gcdf::kTileQ - 1) / gcdf::kTileQ + N;
   job.d = c;
   job.J = J;
-  hipError_t e = gcdf::launch_fused(ctx->net, job, true, J != nullptr, ctx->num_cu, static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = gcdf::launch_fused(ctx->net, job, false, J != nullptr, ctx->num_cu, s);
   return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_eval_grad_csr launch");
 }
 

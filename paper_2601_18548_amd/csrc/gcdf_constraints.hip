@@ -143,6 +143,36 @@ __global__ __launch_bounds__(kPartThreads) void partition_fill_kernel(const floa
   }
 }
 
+// One workgroup: tile_off[0] = 0, tile_off[i+1] = tile_off[i] + ceil(m_i / 64) with
+// m_i = offsets[i+1] - offsets[i] (the gathered tiles of the CSR query).
+__global__ __launch_bounds__(kPartThreads) void csr_tile_offsets_kernel(const int64_t* __restrict__ offsets, int64_t N,
+                                                                        int64_t* __restrict__ tile_off) {
+  __shared__ int64_t buf[kPartThreads];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) {
+    carry = 0;
+    tile_off[0] = 0;
+  }
+  __syncthreads();
+  for (int64_t b = 0; b < N; b += kPartThreads) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t m = i < N ? offsets[i + 1] - offsets[i] : 0;
+    buf[threadIdx.x] = m > 0 ? (m + kTileQ - 1) / kTileQ : 0;
+    __syncthreads();
+    for (int o = 1; o < kPartThreads; o <<= 1) {
+      const int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const int64_t base = carry;
+    if (i < N) tile_off[i + 1] = base + buf[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == kPartThreads - 1) carry = base + buf[kPartThreads - 1];
+    __syncthreads();
+  }
+}
+
 // Thread per row r in [0, total]: row_ptr and the n_conf column indices of row r.
 __global__ void jacobian_pattern_kernel(const int64_t* __restrict__ offsets, int64_t N, int64_t total,
                                         int32_t state_dim, int64_t col0, int64_t* __restrict__ row_ptr,
@@ -255,6 +285,11 @@ hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride
                                  hipStream_t s) {
   hipLaunchKernelGGL(partition_fill_kernel, dim3((unsigned)N), dim3(kPartThreads), 0, s, ref, ref_stride, points, M,
                      radius, offsets, idx, capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_tile_offsets(const int64_t* offsets, int64_t N, int64_t* tile_off, hipStream_t s) {
+  hipLaunchKernelGGL(csr_tile_offsets_kernel, dim3(1), dim3(kPartThreads), 0, s, offsets, N, tile_off);
   return hipGetLastError();
 }
 

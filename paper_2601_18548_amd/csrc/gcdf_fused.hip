@@ -629,7 +629,7 @@ struct TileCtx {
 // One tile: 64 points of knot kk starting at point q0 (dense), or pair-list
 // entries q0 .. q0+63 (pairs).  Every thread of the workgroup calls it; it ends
 // with a barrier, so consecutive calls can reuse the shared memory.
-template <int W, int MODE, bool PAIRS, bool TRAIN = false>
+template <int W, int MODE, bool PAIRS, bool TRAIN = false, bool GATHER = false>
 __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, int want_grad, int64_t kk,
                                              int64_t q0, TileCtx<W, MODE>& tc) {
   using G = Geo<W>;
@@ -641,7 +641,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   float* red = tc.red;
   const Lane<W, MODE>& ln = tc.ln;
   const Bases<W, MODE>& b = tc.b;
-  const int64_t qlimit = PAIRS ? job.npairs : job.Np;
+  const int64_t qlimit = PAIRS ? job.npairs : (GATHER ? job.row_off[kk + 1] : job.Np);
 
   // ---- prologue: base-frame points (+ per-knot arm term of the input layer) ----
   if (tid < kTileQ) {
@@ -664,11 +664,11 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       }
     } else {
       ki = kk;
-      pi = qc;
+      pi = GATHER ? (int64_t)job.pgather[qc] : qc;
     }
     const float* kn = job.knots + ki * kInDim;
     float pxyz[3];
-    if (PAIRS && (uint64_t)pi >= (uint64_t)job.Np) {
+    if ((PAIRS || GATHER) && (uint64_t)pi >= (uint64_t)job.Np) {
       pxyz[0] = pxyz[1] = pxyz[2] = __builtin_nanf("");  // bad point index: NaN results
     } else {
       const float* pt = job.points + pi * 3;
@@ -774,18 +774,20 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     const float dv = vals[0] + *net.b5p;
     const int64_t q = q0 + n;
     const bool valid = q < qlimit;
-    const int64_t out = PAIRS ? q : kk * job.Np + q;
-    if (valid && job.d) job.d[out] = dv;
+    const int64_t out = (PAIRS || GATHER) ? q : kk * job.Np + q;
+    // outputs are streamed with non-temporal stores: written once and never read
+    // here, they would otherwise evict the packed weights from L2
+    if (valid && job.d) __builtin_nontemporal_store(dv, job.d + out);
     if (valid && job.J && want_grad) {
       const float* x = xin + n * XF;
       const float cs = x[3], sn = x[4];
       const float* e = vals + 1;
       float* Jo = job.J + out * kInDim;
-      Jo[0] = -(cs * e[0] - sn * e[1]);
-      Jo[1] = -(sn * e[0] + cs * e[1]);
-      Jo[2] = e[0] * x[1] - e[1] * x[0];
+      __builtin_nontemporal_store(-(cs * e[0] - sn * e[1]), Jo + 0);
+      __builtin_nontemporal_store(-(sn * e[0] + cs * e[1]), Jo + 1);
+      __builtin_nontemporal_store(e[0] * x[1] - e[1] * x[0], Jo + 2);
 #pragma unroll
-      for (int c = 3; c < 9; ++c) Jo[c] = e[c];
+      for (int c = 3; c < 9; ++c) __builtin_nontemporal_store(e[c], Jo + c);
     }
     if constexpr (!PAIRS) {
       if (job.minkey) {
@@ -808,7 +810,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 // ----------------------------------------------------------------------------
 // One-shot kernel: a persistent grid strides over all tiles of one job.
 // ----------------------------------------------------------------------------
-template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false>
+template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false, bool GATHER = false>
 __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
   __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
@@ -817,6 +819,15 @@ __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, c
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (PAIRS) {
       process_tile<W, MODE, true, TRAIN>(net, job, want_grad, 0, tile * kTileQ, tc);
+    } else if constexpr (GATHER) {
+      if (tile >= job.tile_off[job.K]) break;  // the grid is sized by an upper bound
+      int64_t lo = 0, hi = job.K - 1;            // knot: the last i with tile_off[i] <= tile
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (job.tile_off[mid] <= tile) lo = mid; else hi = mid - 1;
+      }
+      process_tile<W, MODE, false, false, true>(net, job, want_grad, lo,
+                                                job.row_off[lo] + (tile - job.tile_off[lo]) * kTileQ, tc);
     } else {
       const int64_t kk = tile / nblk;
       process_tile<W, MODE, false>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
@@ -829,94 +840,171 @@ __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, c
 // order into ServeCtl (pinned host memory); every workgroup walks the sequence
 // with its own cursor and claims tiles with a compare-and-swap on the slot's
 // (seq, count) word, so a late workgroup can never claim tiles of a request
-// that has since been replaced in its slot.  The workgroup that finishes a
-// request's last tile decodes its per-knot minimum, restores the key scratch and
-// publishes completion with a system-scope release store.
+// that has since been replaced in its slot.
+//
+// Memory ordering is paid per request, not per tile: claims are relaxed; a
+// workgroup acquires (system scope) once when it sees new publications; when it
+// leaves a request (its next claim finds no tile left) it releases its output
+// stores at agent scope once and adds the number of tiles it ran to the slot's
+// done counter.  The workgroup whose addition completes the request acquires,
+// decodes the per-knot minimum, restores the key scratch and publishes
+// completion with a system-scope release store.  (Acquire and release at agent
+// or system scope invalidate or write back the L2, which per tile would evict
+// the packed weights.)
 // ----------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ T sys_load(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ T sys_relaxed(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <int W, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, ServeCtl* ctl, ServeDev* dev,
                                                           uint64_t first_seq, uint64_t idle_ticks) {
   __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
-  __shared__ int64_t claim_info[3];  // seq (or -1 to exit), tile, finalize flag
-  __shared__ ServeDesc cur;
+  __shared__ int64_t claim_info[3];  // claimed seq (or -1: exit, -2: none), tile, seq to finalize (or -1)
+  __shared__ ServeDesc cur;          // the request this workgroup is working on
+  __shared__ ServeDesc fin;          // a request this workgroup completes
   TileCtx<W, MODE> tc(lds, net, threadIdx.x);
   const int tid = threadIdx.x;
   uint64_t seq = first_seq;  // this workgroup's cursor in the request sequence
   uint64_t cur_seq = ~0ull;
   uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
-  const uint32_t slots = sys_load(&ctl->slots);
-  // thread 0's view of the queue: host memory is read only when the cursor has
-  // caught up with the cached published count, or for a new request's size
+  const uint32_t slots = sys_relaxed(&ctl->slots);
+  // thread 0's view of the queue
   uint64_t pub = 0, nt_seq = ~0ull;
   int64_t ntiles = 0;
+  uint64_t open_count = 0;  // tiles of request cur_seq run here and not yet reported
   int backoff = 1;
   while (true) {
     if (tid == 0) {
-      int64_t got_seq = -1, got_tile = 0;
+      int64_t got_seq = -1, got_tile = 0, fin_seq = -1;
       while (true) {
-        if (seq >= pub) pub = sys_load(&ctl->published);
+        if (seq >= pub) {
+          const uint64_t p = sys_relaxed(&ctl->published);
+          if (p > pub) {
+            pub = p;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // system scope: the new descriptors
+          }
+        }
         if (seq < pub) {
           const uint32_t s = (uint32_t)(seq % slots);
           if (nt_seq != seq) {
-            ntiles = sys_load(&ctl->desc[s].ntiles);
+            ntiles = sys_relaxed(&ctl->desc[s].ntiles);
             nt_seq = seq;
           }
+          // Claim word of the slot: (request tag << 32) | tiles handed out.  The first
+          // claimant of a request re-tags the word with a compare-and-swap; every other
+          // claim is a fetch_add, which never has to be retried.
           unsigned long long v = __hip_atomic_load(&dev->claim[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t s32 = seq & 0xffffffffull;
           bool moved_on = false;
           while (true) {
             const uint64_t vs = v >> 32, vc = v & 0xffffffffull;
-            const uint64_t s32 = seq & 0xffffffffull;
-            unsigned long long nv;
-            int64_t t;
             if (vs > s32) { moved_on = true; break; }  // slot already reused: seq is complete
-            if (vs < s32) { nv = (s32 << 32) | 1ull; t = 0; }   // first claim of request seq
-            else { if ((int64_t)vc >= ntiles) { moved_on = true; break; } nv = v + 1; t = (int64_t)vc; }
-            if (__hip_atomic_compare_exchange_strong(&dev->claim[s], &v, nv, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) {
-              got_seq = (int64_t)seq;
-              got_tile = t;
+            if (vs < s32) {                            // first claim of request seq
+              if (__hip_atomic_compare_exchange_strong(&dev->claim[s], &v, (s32 << 32) | 1ull, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                got_seq = (int64_t)seq;
+                got_tile = 0;
+                break;
+              }
+              continue;  // v now holds the current word
+            }
+            if ((int64_t)vc >= ntiles) { moved_on = true; break; }
+            const unsigned long long w =
+                __hip_atomic_fetch_add(&dev->claim[s], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t ws = w >> 32, wc = w & 0xffffffffull;
+            if (ws == s32) {
+              if ((int64_t)wc < ntiles) { got_seq = (int64_t)seq; got_tile = (int64_t)wc; }
+              else moved_on = true;
               break;
             }
+            // Between the load and the add, request seq finished and a later request
+            // took the slot: the add handed out tile wc of that request, which must be
+            // run here.  Its tag is the low half of its sequence number.
+            const uint64_t later = seq + ((ws - s32) & 0xffffffffull);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // its descriptor
+            const int64_t lnt = sys_relaxed(&ctl->desc[s].ntiles);
+            // (no tiles of seq can be unreported here: seq could not have completed)
+            seq = later;
+            if (pub < later + 1) pub = later + 1;
+            nt_seq = later;
+            ntiles = lnt;
+            if ((int64_t)wc < lnt) { got_seq = (int64_t)later; got_tile = (int64_t)wc; }
+            else moved_on = true;
+            break;
           }
           if (got_seq >= 0) break;
-          if (moved_on) ++seq;
+          if (moved_on) {
+            if (open_count && cur_seq == seq) {
+              // leaving request seq: release this workgroup's stores and atomics, then report
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+              const unsigned long long done =
+                  __hip_atomic_fetch_add(&dev->done[s], open_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                  open_count;
+              open_count = 0;
+              if (done == cur.done_target) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every contributor's results
+                fin = cur;
+                fin_seq = (int64_t)seq;
+              }
+            }
+            ++seq;
+            if (fin_seq >= 0) break;
+          }
         } else {
-          if (sys_load(&ctl->stop) || __builtin_amdgcn_s_memrealtime() - idle_since > idle_ticks) break;
+          if (sys_relaxed(&ctl->stop) || __builtin_amdgcn_s_memrealtime() - idle_since > idle_ticks) break;
           // idle: back off up to ~4 us between polls of host memory
           for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(16);
           backoff = backoff < 8 ? 2 * backoff : 8;
         }
       }
       backoff = 1;
-      claim_info[0] = got_seq;
+      // -1: exit (no claimable work), -2: nothing claimed but a request to finalize
+      claim_info[0] = got_seq >= 0 ? got_seq : (fin_seq >= 0 ? -2 : -1);
       claim_info[1] = got_tile;
+      claim_info[2] = fin_seq;
       if (got_seq >= 0 && (uint64_t)got_seq != cur_seq) {
         const ServeDesc* d = &ctl->desc[got_seq % slots];
-        cur.knots = sys_load(&d->knots);
-        cur.points = sys_load(&d->points);
-        cur.K = sys_load(&d->K);
-        cur.Np = sys_load(&d->Np);
-        cur.nblk = sys_load(&d->nblk);
-        cur.ntiles = sys_load(&d->ntiles);
-        cur.done_target = sys_load(&d->done_target);
-        cur.d = sys_load(&d->d);
-        cur.J = sys_load(&d->J);
-        cur.minkey = sys_load(&d->minkey);
-        cur.dmin = sys_load(&d->dmin);
-        cur.argmin = sys_load(&d->argmin);
-        cur.want_grad = sys_load(&d->want_grad);
+        cur.knots = sys_relaxed(&d->knots);
+        cur.points = sys_relaxed(&d->points);
+        cur.K = sys_relaxed(&d->K);
+        cur.Np = sys_relaxed(&d->Np);
+        cur.nblk = sys_relaxed(&d->nblk);
+        cur.ntiles = sys_relaxed(&d->ntiles);
+        cur.done_target = sys_relaxed(&d->done_target);
+        cur.d = sys_relaxed(&d->d);
+        cur.J = sys_relaxed(&d->J);
+        cur.minkey = sys_relaxed(&d->minkey);
+        cur.dmin = sys_relaxed(&d->dmin);
+        cur.argmin = sys_relaxed(&d->argmin);
+        cur.want_grad = sys_relaxed(&d->want_grad);
         cur.seq = (uint64_t)got_seq;
+        cur_seq = (uint64_t)got_seq;
       }
+      if (got_seq >= 0) ++open_count;
     }
     __syncthreads();
     const int64_t gs = claim_info[0];
-    if (gs < 0) break;
-    cur_seq = (uint64_t)gs;
+    if (claim_info[2] >= 0) {
+      // this workgroup completed request fin.seq: per-knot minimum, key scratch restored
+      if (fin.dmin) {
+        for (int64_t k = tid; k < fin.K; k += kThreads) {
+          const unsigned long long key = __hip_atomic_load(fin.minkey + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t o = (uint32_t)(key >> 32);
+          const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+          fin.dmin[k] = __uint_as_float(u);
+          fin.argmin[k] = key == ~0ull ? 0 : (int32_t)(uint32_t)(key & 0xffffffffu);
+          fin.minkey[k] = ~0ull;
+        }
+      }
+      __threadfence_system();
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_store(&ctl->complete[fin.seq % slots], fin.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (gs == -1) break;
+    if (gs < 0) continue;
     const int64_t t = claim_info[1];
     Job job{};
     job.knots = cur.knots;
@@ -928,33 +1016,6 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
     job.minkey = cur.minkey;
     const int64_t kk = t / cur.nblk;
     process_tile<W, MODE, false>(net, job, cur.want_grad, kk, (t - kk * cur.nblk) * kTileQ, tc);
-    // every thread's stores and atomics of this tile are issued; publish them
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t s = (uint32_t)(cur.seq % slots);
-      const unsigned long long done =
-          __hip_atomic_fetch_add(&dev->done[s], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-      claim_info[2] = done == cur.done_target ? 1 : 0;
-    }
-    __syncthreads();
-    if (claim_info[2]) {
-      // last tile of the request: per-knot minimum, restore the key scratch
-      if (cur.dmin) {
-        for (int64_t k = tid; k < cur.K; k += kThreads) {
-          const unsigned long long key = __hip_atomic_load(cur.minkey + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const uint32_t o = (uint32_t)(key >> 32);
-          const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
-          cur.dmin[k] = __uint_as_float(u);
-          cur.argmin[k] = key == ~0ull ? 0 : (int32_t)(uint32_t)(key & 0xffffffffu);
-          cur.minkey[k] = ~0ull;
-        }
-      }
-      __threadfence_system();
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_store(&ctl->complete[cur.seq % slots], cur.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
     if (tid == 0) idle_since = __builtin_amdgcn_s_memrealtime();
   }
 }
@@ -1120,11 +1181,11 @@ template <int W, int MODE, bool PAIRS>
 static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, int num_cu, hipStream_t s) {
   constexpr int OCC = 1;
   const int64_t ntiles = PAIRS ? (job.npairs + kTileQ - 1) / kTileQ
-                               : job.K * ((job.Np + kTileQ - 1) / kTileQ);
+                               : (job.tile_off ? job.ntiles_bound : job.K * ((job.Np + kTileQ - 1) / kTileQ));
   if (ntiles <= 0) return hipSuccess;
   const int64_t slots = (int64_t)num_cu * OCC;
   const int grid = (int)(ntiles < slots ? ntiles : slots);
-  if constexpr (PAIRS && W == 256) {  // training (weight gradients) is built for width 256
+  if constexpr (PAIRS && W == 256 && MODE != kBF16X2) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
       hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3(kThreads), 0, s, net, job, 1,
                          ntiles);
@@ -1132,8 +1193,15 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
     }
   }
   if (job.dumpH) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC>), dim3(grid), dim3(kThreads), 0, s, net, job,
-                       want_grad ? 1 : 0, ntiles);
+  if constexpr (!PAIRS) {
+    if (job.tile_off) {
+      hipLaunchKernelGGL((fused_query<W, MODE, false, OCC, false, true>), dim3(grid), dim3(kThreads), 0, s, net, job,
+                         want_grad ? 1 : 0, ntiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC>), dim3(grid), dim3(kThreads), 0, s, net, job,
+                     want_grad ? 1 : 0, ntiles);
   return hipGetLastError();
 }
 

@@ -42,6 +42,14 @@ struct Job {
   const int64_t* csr_off;
   int64_t csr_n;
   const int32_t* csr_idx;
+  // Gathered knot tiles (dense mode, when tile_off is set): knot i owns rows
+  // row_off[i] .. row_off[i+1]-1, row r pairing it with point pgather[r]; its rows
+  // form tile_off[i+1] - tile_off[i] tiles of up to 64 (tile_off[0] = 0), so no tile
+  // mixes knots; d and J are indexed by row; ntiles_bound >= tile_off[K] sizes the grid.
+  const int64_t* tile_off;
+  const int64_t* row_off;
+  const int32_t* pgather;
+  int64_t ntiles_bound;
   float* d;                  // dense: [K][Np]; pairs: [npairs]      (nullable)
   float* J;                  // dense: [K][Np][9]; pairs: [npairs][9] (nullable)
   unsigned long long* minkey;// dense only: [K] ordered (distance, index) keys (nullable)
@@ -78,6 +86,8 @@ hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_strid
 hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
                                  float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
                                  hipStream_t s);
+// tile_off[0] = 0, tile_off[i+1] = tile_off[i] + ceil((offsets[i+1] - offsets[i]) / 64).
+hipError_t launch_csr_tile_offsets(const int64_t* offsets, int64_t N, int64_t* tile_off, hipStream_t s);
 // Sparsity pattern of the stacked constraint Jacobian: row_ptr[r] = n_conf * r (r <= total),
 // cols[n_conf * r + c] = col0 + state_dim * knot(r) + c.
 hipError_t launch_jacobian_pattern(const int64_t* offsets, int64_t N, int64_t total, int32_t state_dim, int64_t col0,
