@@ -259,9 +259,23 @@ gcdf_status gcdf_train_forward(gcdf_trainer* tr, const float* params, const floa
 
 /* grad_params (device float32[gcdf_param_count(W)], overwritten) =
  * sum_i grad_d[i] * d d_i / d params: the reverse mode of the network, seeded
- * with the per-sample loss gradient.  Deterministic (fixed reduction order). */
+ * with the per-sample loss gradient.  Deterministic (fixed reduction order).
+ * reuse_packed != 0 asserts that params (same pointer) has not changed since
+ * the last forward or backward call on this trainer, whose packed copy of the
+ * weights is then reused; with 0 (or another pointer) the weights are packed
+ * again. */
 gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
-                                int64_t B, const float* grad_d, float* grad_params, void* stream);
+                                int64_t B, const float* grad_d, float* grad_params, int32_t reuse_packed,
+                                void* stream);
+
+/* One Adam step (the optimiser of the paper's training, Sec. V-A) over n device
+ * floats, in torch.optim.Adam's arithmetic (no weight decay, no amsgrad):
+ *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+ *   p -= (lr / (1 - beta1^step)) * m / (sqrt(v) / sqrt(1 - beta2^step) + eps).
+ * params, m, v are updated in place (m and v start at zero); step counts from 1.
+ * EINVAL: NULL pointers, n < 0, step < 1, lr or eps not finite, beta outside [0, 1). */
+gcdf_status gcdf_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int64_t step, void* stream);
 
 #ifdef __cplusplus
 }

@@ -326,8 +326,8 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 // ----------------------------------------------------------------------------
 template <int W, int MODE>
 __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {
-  for (int f = threadIdx.x; f < W; f += kThreads) {
-    if constexpr (MODE == kFP32) {
+  for (int f = threadIdx.x; f < W && MODE == kFP32; f += kThreads) {
+    {
       const float* a = reinterpret_cast<const float*>(act);
       float* o = static_cast<float*>(dst) + (int64_t)f * ldb + q0;
 #pragma unroll 4
@@ -340,16 +340,35 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
         }
         *reinterpret_cast<f32x4*>(o + n) = v;
       }
-    } else {
-      const __bf16* a = reinterpret_cast<const __bf16*>(act);
-      __bf16* o = static_cast<__bf16*>(dst) + (int64_t)f * ldb + q0;
-      const int base = (((f >> 4) * 2 + ((f & 15) >> 3)) * 1024) / 2 + (f & 7);
-#pragma unroll 2
-      for (int n = 0; n < kTileQ; n += 8) {
-        bf16x8 v;
+    }
+  }
+  if constexpr (MODE != kFP32) {
+    // The hi plane holds, for each group of 8 features and each query n, the 8
+    // features' values as one 16-byte word.  A thread reads the 8x8 block of 8
+    // consecutive queries, transposes it in registers and writes 8 feature rows of
+    // 8 queries (16 bytes each).
+    typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+    const char* a = act;
+    constexpr int NG = W / 8;  // feature groups
+    for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += kThreads) {
+      const int g8 = t % NG, nb = t / NG;
+      const int gbyte = ((g8 >> 1) * 2 + (g8 & 1)) * 1024;  // 16-feature block, 8-feature half
+      u32x4 m[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = n + u < nvalid ? a[base + (n + u) * 8] : (__bf16)0.f;
-        *reinterpret_cast<bf16x8*>(o + n) = v;
+      for (int j = 0; j < 8; ++j) {
+        const int n = nb * 8 + j;
+        m[j] = n < nvalid ? *reinterpret_cast<const u32x4*>(a + gbyte + n * 16) : u32x4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int fl = 0; fl < 8; ++fl) {  // feature 8 g8 + fl: halves of word fl/2 of every m[j]
+        u32x4 row;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const uint32_t x0 = m[2 * jj][fl >> 1], x1 = m[2 * jj + 1][fl >> 1];
+          row[jj] = (fl & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
+        }
+        __bf16* o = static_cast<__bf16*>(dst) + (int64_t)(8 * g8 + fl) * ldb + q0 + nb * 8;
+        *reinterpret_cast<u32x4*>(o) = row;
       }
     }
   }
@@ -1328,48 +1347,122 @@ hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, 
   return hipGetLastError();
 }
 
-// One workgroup per row; each thread sums a fixed stride of samples, then a fixed
-// tree over the workgroup.
+// Row reductions over the batch in two fixed-order passes.  Pass 1: grid (row
+// quad, chunk of kRrChunk samples); wave w of a workgroup takes one row, each lane
+// 8 consecutive samples per step (one 16-byte load of A), and the wave's sums go
+// to partial[chunk][row][c] after a butterfly reduction.  Pass 2 adds the chunks
+// in index order.  The result does not depend on scheduling.
+constexpr int kRrChunk = 4096;
+constexpr int kRrMaxC = 9;
+
+int rr_chunks(int64_t B) { return (int)((B + kRrChunk - 1) / kRrChunk); }
+
 template <bool BF>
-__global__ __launch_bounds__(256) void row_reduce_kernel(const void* __restrict__ Av, int64_t lda, int64_t B,
-                                                         const float* __restrict__ V, int64_t ldv, int C,
-                                                         float* __restrict__ out, float* __restrict__ bias) {
-  constexpr int kMaxC = 9;
-  __shared__ float red[kMaxC + 1][256];
-  const int r = blockIdx.x, t = threadIdx.x;
-  float acc[kMaxC + 1];
+__device__ __forceinline__ float rr_load(const void* A, int64_t idx) {
+  if constexpr (BF) return (float)static_cast<const __bf16*>(A)[idx];
+  else return static_cast<const float*>(A)[idx];
+}
+
+template <bool BF>
+__global__ __launch_bounds__(256) void rr_partial_kernel(const void* __restrict__ Av, int64_t lda, int rows, int64_t B,
+                                                          const float* __restrict__ V, int64_t ldv, int C,
+                                                          float* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + wave;
+  if (r >= rows) return;
+  const int64_t i0 = (int64_t)blockIdx.y * kRrChunk;
+  const int64_t i1 = i0 + kRrChunk < B ? i0 + kRrChunk : B;
+  float acc[kRrMaxC + 1];
 #pragma unroll
-  for (int c = 0; c <= kMaxC; ++c) acc[c] = 0.f;
-  for (int64_t i = t; i < B; i += 256) {
-    const float a = BF ? (float)static_cast<const __bf16*>(Av)[(int64_t)r * lda + i]
-                       : static_cast<const float*>(Av)[(int64_t)r * lda + i];
-    acc[kMaxC] += a;
+  for (int c = 0; c <= kRrMaxC; ++c) acc[c] = 0.f;
+  const int64_t arow = (int64_t)r * lda;
+  for (int64_t i = i0 + lane * 8; i < i1; i += 64 * 8) {
+    float a[8];
+    if (i + 8 <= i1) {
+      if constexpr (BF) {
+        typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
+        const v8 x = *reinterpret_cast<const v8*>(static_cast<const __bf16*>(Av) + arow + i);
 #pragma unroll
-    for (int c = 0; c < kMaxC; ++c)
-      if (c < C) acc[c] += a * V[(int64_t)c * ldv + i];
+        for (int u = 0; u < 8; ++u) a[u] = (float)x[u];
+      } else {
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + arow + i);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + arow + i + 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = x0[u];
+          a[4 + u] = x1[u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = i + u < i1 ? rr_load<BF>(Av, arow + i + u) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[kRrMaxC] += a[u];
+    const bool full = i + 8 <= i1;
+    for (int c = 0; c < C; ++c) {
+      const float* v = V + (int64_t)c * ldv + i;
+      float vv[8];
+      if (full && ldv) {  // rows of V start 32-byte aligned (ldv a multiple of 64)
+        const f32x4 v0 = *reinterpret_cast<const f32x4*>(v);
+        const f32x4 v1 = *reinterpret_cast<const f32x4*>(v + 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          vv[u] = v0[u];
+          vv[4 + u] = v1[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[u] = i + u < i1 ? v[u] : 0.f;
+      }
+      float t = acc[c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += a[u] * vv[u];
+      acc[c] = t;
+    }
   }
 #pragma unroll
-  for (int c = 0; c <= kMaxC; ++c) red[c][t] = acc[c];
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (t < w)
+  for (int c = 0; c <= kRrMaxC; ++c) {
+    float t = acc[c];
 #pragma unroll
-      for (int c = 0; c <= kMaxC; ++c) red[c][t] += red[c][t + w];
-    __syncthreads();
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    acc[c] = t;
   }
-  if (t == 0) {
-    for (int c = 0; c < C; ++c) out[(int64_t)r * C + c] = red[c][0];
-    if (bias) bias[r] = red[kMaxC][0];
+  if (lane == 0) {
+    float* out = partial + ((int64_t)blockIdx.y * rows + r) * (kRrMaxC + 1);
+#pragma unroll
+    for (int c = 0; c <= kRrMaxC; ++c) out[c] = acc[c];
+  }
+}
+
+__global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, int rows, int C, float* __restrict__ out,
+                              float* __restrict__ bias) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = (int)(t / (kRrMaxC + 1)), c = (int)(t % (kRrMaxC + 1));
+  if (r >= rows || (c >= C && c != kRrMaxC)) return;
+  float s = 0.f;
+  for (int k = 0; k < nchunks; ++k) s += partial[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
+  if (c == kRrMaxC) {
+    if (bias) bias[r] = s;
+  } else if (out) {
+    out[(int64_t)r * C + c] = s;
   }
 }
 
 hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
-                             int64_t ldv, int C, float* out, float* bias, hipStream_t s) {
-  if (C > 9) return hipErrorInvalidValue;
+                             int64_t ldv, int C, float* out, float* bias, float* partial, hipStream_t s) {
+  if (C > kRrMaxC || rows <= 0 || B <= 0) return hipErrorInvalidValue;
+  const int nch = rr_chunks(B);
+  const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)nch);
   if (a_is_bf16)
-    hipLaunchKernelGGL(row_reduce_kernel<true>, dim3(rows), dim3(256), 0, s, A, lda, B, V, ldv, C, out, bias);
+    hipLaunchKernelGGL(rr_partial_kernel<true>, grid, dim3(256), 0, s, A, lda, rows, B, V, ldv, C, partial);
   else
-    hipLaunchKernelGGL(row_reduce_kernel<false>, dim3(rows), dim3(256), 0, s, A, lda, B, V, ldv, C, out, bias);
+    hipLaunchKernelGGL(rr_partial_kernel<false>, grid, dim3(256), 0, s, A, lda, rows, B, V, ldv, C, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)rows * (kRrMaxC + 1);
+  hipLaunchKernelGGL(rr_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nch, rows, C, out,
+                     bias);
   return hipGetLastError();
 }
 

@@ -167,9 +167,15 @@ hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, int64_t ldb, int64_t B, float* partial,
                              int nchunks, float* out, hipStream_t s);
 int wgrad_chunks(int64_t B);
-// For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C, V row stride ldv)
-// and bias[r] = sum_i A[r][i] (bias may be NULL), i < B, fixed-order sums.
+// For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
+// ldv) and bias[r] = sum_i A[r][i] (out / bias may be NULL), i < B; chunked partial
+// sums in `partial` (rr_chunks(B) * rows * 10 floats) added in a fixed order.
+int rr_chunks(int64_t B);
 hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
-                             int64_t ldv, int C, float* out, float* bias, hipStream_t s);
+                             int64_t ldv, int C, float* out, float* bias, float* partial, hipStream_t s);
+
+// Adam step over n floats (see gcdf_adam_step).
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, hipStream_t s);
 
 }  // namespace gcdf

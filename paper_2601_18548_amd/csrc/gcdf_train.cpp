@@ -10,6 +10,8 @@
 //           (fixed-order row reductions).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +30,7 @@ struct gcdf_trainer {
   void* dumpG = nullptr;
   float* dumpV = nullptr;
   float* partial = nullptr;
+  const float* packed_from = nullptr;  // params pointer of the last packing
 };
 
 namespace {
@@ -78,6 +81,7 @@ hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
       e = gcdf::pack_matrix(params + o.Wl[l], base + tr->off_m + (size_t)(3 + l) * tr->mbytes, tr->W, tr->mode, true, s);
   }
   tr->net.b5p = params + o.b5;
+  tr->packed_from = e == hipSuccess ? params : nullptr;
   return e;
 }
 
@@ -123,8 +127,9 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(&tr->dumpH, dump);
   if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
-  if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void**>(&tr->partial), (size_t)gcdf::wgrad_chunks(max_batch) * W * W * 4);
+  const size_t part = std::max((size_t)gcdf::wgrad_chunks(max_batch) * W * W,
+                                (size_t)gcdf::rr_chunks(max_batch) * W * 10);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->partial), part * 4);
   if (e != hipSuccess) {
     gcdf_trainer_destroy(tr);
     return tfail(GCDF_ENOMEM, "trainer allocation failed: %s", hipGetErrorString(e));
@@ -174,7 +179,7 @@ gcdf_status gcdf_train_forward(gcdf_trainer* tr, const float* params, const floa
 }
 
 gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
-                                int64_t B, const float* grad_d, float* grad, void* stream) {
+                                int64_t B, const float* grad_d, float* grad, int32_t reuse_packed, void* stream) {
   gcdf_status st = check(tr, params, knots, points, B);
   if (st != GCDF_OK) return st;
   if (!grad_d || !grad) return tfail(GCDF_EINVAL, "grad_d or grad_params is NULL");
@@ -187,7 +192,7 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   auto H = [&](int l) { return static_cast<const char*>(tr->dumpH) + l * layer; };
   auto G = [&](int l) { return static_cast<const char*>(tr->dumpG) + l * layer; };
   const bool bf = tr->mode != GCDF_FP32;
-  hipError_t e = pack(tr, params, s);
+  hipError_t e = (reuse_packed && tr->packed_from == params) ? hipSuccess : pack(tr, params, s);
   gcdf::Job job{};
   job.knots = knots;
   job.points = points;
@@ -205,15 +210,31 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4
   for (int l = 0; l < 3 && e == hipSuccess; ++l)
     e = gcdf::launch_wgrad_gemm(G(l + 1), H(l), W, gmode, tr->ldb, B, tr->partial, nch, grad + o.Wl[l], s);
-  // input layer: dW1 = G_1 V^T, db1 = sum G_1
+  // input layer: dW1 = G_1 V^T, db1 = sum G_1 (the partial buffer is free again:
+  // each reduction follows the previous one on the stream)
+  float* part = tr->partial;
   if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(G(0), bf, tr->ldb, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, s);
+    e = gcdf::launch_row_reduce(G(0), bf, tr->ldb, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, part, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::launch_row_reduce(G(l + 1), bf, tr->ldb, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], s);
+    e = gcdf::launch_row_reduce(G(l + 1), bf, tr->ldb, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], part, s);
   // output layer: dw_out = H_4 seed, db_out = sum seed
-  if (e == hipSuccess) e = gcdf::launch_row_reduce(H(3), bf, tr->ldb, W, B, grad_d, 0, 1, grad + o.w5, nullptr, s);
-  if (e == hipSuccess) e = gcdf::launch_row_reduce(grad_d, false, 0, 1, B, nullptr, 0, 0, nullptr, grad + o.b5, s);
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(H(3), bf, tr->ldb, W, B, grad_d, 0, 1, grad + o.w5, nullptr, part, s);
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(grad_d, false, 0, 1, B, nullptr, 0, 0, nullptr, grad + o.b5, part, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
+}
+
+gcdf_status gcdf_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int64_t step, void* stream) {
+  if (!params || !grad || !m || !v) return tfail(GCDF_EINVAL, "NULL pointer to gcdf_adam_step");
+  if (n < 0 || step < 1) return tfail(GCDF_EINVAL, "n must be >= 0 and step >= 1");
+  if (!std::isfinite(lr) || !std::isfinite(eps) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return tfail(GCDF_EINVAL, "lr / eps must be finite and betas in [0, 1)");
+  if (n == 0) return GCDF_OK;
+  const hipError_t e = gcdf::launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step,
+                                         static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_adam_step: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -52,18 +52,31 @@ class Trainer:
         B = knots.shape[0]
         if d is None:
             d = torch.empty(B, dtype=torch.float32, device=knots.device)
+        self._packed = None
         _check(library().gcdf_train_forward(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
                                             d.data_ptr(), _stream(stream)))
+        self._packed = (params, params._version)  # the weights this call packed
         return d
 
-    def backward(self, params, knots, points, grad_d, grad=None, stream=None):
+    def packed_is_current(self, params) -> bool:
+        """True if the library's packed weights were made from `params` as it is now."""
+        pk = getattr(self, "_packed", None)
+        return pk is not None and pk[0] is params and pk[1] == params._version
+
+    def backward(self, params, knots, points, grad_d, grad=None, reuse_packed: bool = False, stream=None):
+        """reuse_packed: params is unchanged since the last forward/backward call
+        (the weights packed then are reused)."""
         import torch
 
         B = knots.shape[0]
         if grad is None:
             grad = torch.empty_like(params)
+        reuse = bool(reuse_packed) and self.packed_is_current(params)
+        self._packed = None
         _check(library().gcdf_train_backward(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
-                                             grad_d.data_ptr(), grad.data_ptr(), _stream(stream)))
+                                             grad_d.data_ptr(), grad.data_ptr(), 1 if reuse else 0,
+                                             _stream(stream)))
+        self._packed = (params, params._version)
         return grad
 
 
@@ -89,12 +102,16 @@ def _make_function():
             d = trainer.forward(params, knots, points)
             ctx.save_for_backward(params, knots, points)
             ctx.trainer = trainer
+            ctx.params = params
             return d
 
         @staticmethod
         def backward(ctx, grad_d):
             params, knots, points = ctx.saved_tensors
-            g = ctx.trainer.backward(params, knots, points, grad_d.contiguous().float())
+            # reuse the weights packed by the forward if nothing has packed since and
+            # the parameters were not modified in place
+            g = ctx.trainer.backward(ctx.params, knots, points, grad_d.contiguous().float(), reuse_packed=True)
+            ctx.params = None
             return g, None, None, None
 
     return GcdfNet
@@ -109,6 +126,48 @@ def gcdf_net(params, knots, points, trainer):
     if _fn is None:
         _fn = _make_function()
     return _fn.apply(params, knots, points, trainer)
+
+
+class Adam:
+    """Adam over one flat FP32 parameter tensor with the library's update kernel
+    (gcdf_adam_step: torch.optim.Adam's arithmetic, one launch over the whole
+    vector).  Minimal optimiser interface: zero_grad(), step()."""
+
+    def __init__(self, params, lr: float = 5e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+        import torch
+
+        if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()):
+            raise ValueError("params must be a contiguous float32 CUDA tensor")
+        self.params, self.lr, self.betas, self.eps = params, float(lr), (float(betas[0]), float(betas[1])), float(eps)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.t = 0
+
+    def zero_grad(self, set_to_none: bool = False):
+        if self.params.grad is not None:
+            if set_to_none:
+                self.params.grad = None
+            else:
+                self.params.grad.zero_()
+
+    def step(self, stream=None):
+        g = self.params.grad
+        if g is None:
+            return
+        self.t += 1
+        p = self.params.detach()
+        _check(library().gcdf_adam_step(p.data_ptr(), g.contiguous().data_ptr(), self.m.data_ptr(),
+                                        self.v.data_ptr(), p.numel(), self.lr, self.betas[0], self.betas[1],
+                                        self.eps, self.t, _stream(stream)))
+        # the kernel wrote the parameters in place: let torch (and Trainer's packed-weight
+        # check) see a new version
+        import torch
+
+        torch.autograd.graph.increment_version(self.params)
+
+
+def adam(params, lr: float = 5e-3, betas=(0.9, 0.999)):
+    return Adam(params, lr=lr, betas=betas)
 
 
 def mse_step(params, opt, trainer, knots, points, targets):

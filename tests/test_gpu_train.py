@@ -111,7 +111,50 @@ def test_autograd_function_and_adam_reduce_the_loss(tr_mod):
     gd = (2.0 * (d.detach() - y) / B).contiguous()
     direct = trainer.backward(params.detach(), kt, pt, gd)
     assert torch.equal(params.grad, direct)
-    opt = torch.optim.Adam([params], lr=5e-3)
+    opt = tr_mod.adam(params, lr=5e-3)
     losses = [tr_mod.mse_step(params, opt, trainer, kt, pt, y).item() for _ in range(30)]
     print("loss %.4f -> %.4f" % (losses[0], losses[-1]), flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_native_adam_matches_torch_adam(tr_mod):
+    """gcdf_adam_step against torch.optim.Adam (CPU, float64) over 25 steps."""
+    rng = np.random.default_rng(11)
+    n = 100_003
+    p0 = rng.normal(size=n).astype(np.float32)
+    grads = [rng.normal(scale=10.0 ** rng.uniform(-4, 1), size=n).astype(np.float32) for _ in range(25)]
+    p = torch.from_numpy(p0.copy()).cuda().requires_grad_(True)
+    opt = tr_mod.Adam(p, lr=5e-3, betas=(0.9, 0.999), eps=1e-8)
+    ref = torch.from_numpy(p0.astype(np.float64)).requires_grad_(True)
+    ropt = torch.optim.Adam([ref], lr=5e-3, betas=(0.9, 0.999), eps=1e-8, foreach=False)
+    for g in grads:
+        p.grad = torch.from_numpy(g).cuda()
+        opt.step()
+        ref.grad = torch.from_numpy(g.astype(np.float64))
+        ropt.step()
+    got = p.detach().cpu().numpy().astype(np.float64)
+    want = ref.detach().numpy()
+    # each step moves a parameter by at most ~lr; FP32 rounding of the update
+    assert np.abs(got - want).max() <= 1e-5
+    assert np.abs(got - p0).max() > 1e-2  # it did move
+
+
+def test_packed_weights_reused_only_when_unchanged(tr_mod):
+    """The autograd backward reuses the forward's packed weights; a direct backward
+    with other parameters in between forces a repack (same gradients as a fresh
+    trainer either way)."""
+    w1 = wl.weights(256, seed=36, bf16_hidden=False)
+    w2 = wl.weights(256, seed=37, bf16_hidden=False)
+    k, p, y = batch(1000, 12)
+    kt, pt, yt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(y).cuda()
+    trainer = tr_mod.Trainer(256, "fp32", max_batch=1000)
+    a = tr_mod.flat_params(w1).requires_grad_(True)
+    b = tr_mod.flat_params(w2)
+    d = tr_mod.gcdf_net(a, kt, pt, trainer)
+    gd = (2.0 * (d.detach() - yt) / 1000).contiguous()
+    trainer.backward(b, kt, pt, gd)  # packs b
+    loss = ((d - yt) ** 2).mean()
+    loss.backward()  # must repack a
+    fresh = tr_mod.Trainer(256, "fp32", max_batch=1000)
+    want = fresh.backward(a.detach(), kt, pt, gd)
+    assert torch.equal(a.grad, want)
