@@ -1258,11 +1258,33 @@ constexpr int kWgChunk = 2048;  // batch samples per chunk
 int wgrad_chunks(int64_t B) { return (int)((B + kWgChunk - 1) / kWgChunk); }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void wgrad_gemm_kernel(const void* __restrict__ Gv, const void* __restrict__ Hv,
-                                                         int Wd, int64_t ldb, int64_t B, float* __restrict__ partial) {
+struct WgFrag;
+template <>
+struct WgFrag<kFP32> {
+  f32x4 a[2], b[2];
+};
+template <>
+struct WgFrag<kBF16> {
+  bf16x8 a[2], b[2];
+};
+
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8); the
+// mapping below keeps the 4 output tiles of one (GEMM, chunk) on one XCD, so the
+// chunk's rows of G and H come from HBM once and are shared through that L2.
+template <int MODE>
+__global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd, int64_t ldb, int64_t B, int nchunks,
+                                                         float* __restrict__ partial) {
+  constexpr int kXcd = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tiles_n = Wd / 128;
-  const int tile = blockIdx.x % (tiles_n * tiles_n), chunk = blockIdx.x / (tiles_n * tiles_n);
+  const int tiles_n = Wd / 128, ntile = tiles_n * tiles_n;
+  const int64_t groups = (int64_t)jobs.n * nchunks;  // (GEMM, chunk) pairs
+  const int64_t b = blockIdx.x;
+  const int64_t per_xcd = (groups + kXcd - 1) / kXcd;  // groups served by each XCD
+  const int64_t local = b / kXcd, xcd = b % kXcd;
+  const int64_t grp = xcd * per_xcd + local / ntile;
+  if (grp >= groups) return;
+  const int tile = (int)(local % ntile);
+  const int job = (int)(grp / nchunks), chunk = (int)(grp % nchunks);
   const int f0 = (tile / tiles_n) * 128 + (wave >> 1) * 64;  // rows of out (G features)
   const int g0 = (tile % tiles_n) * 128 + (wave & 1) * 64;   // cols of out (H features)
   const int64_t i0 = (int64_t)chunk * kWgChunk;
@@ -1275,44 +1297,52 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const void* __restrict_
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][c][j] = 0.f;
   const int m = lane & 31, kh = lane >> 5;
-  if constexpr (MODE == kFP32) {
-    const float* G = static_cast<const float*>(Gv);
-    const float* H = static_cast<const float*>(Hv);
-    // lane (m, kh) takes 4 consecutive samples i .. i+3 with i = i8 + 4 kh; MFMA q pairs sample i8 + 4 kh + q
-    for (int64_t i8 = i0; i8 < i1; i8 += 8) {
-      f32x4 a[2], bb[2];
+  using E = typename std::conditional<MODE == kFP32, float, __bf16>::type;
+  constexpr int KS = MODE == kFP32 ? 8 : 16;  // samples per step
+  const E* G = static_cast<const E*>(jobs.G[job]);
+  const E* H = static_cast<const E*>(jobs.H[job]);
+  const E* ga[2] = {G + (int64_t)(f0 + m) * ldb + (KS / 2) * kh, G + (int64_t)(f0 + 32 + m) * ldb + (KS / 2) * kh};
+  const E* hb[2] = {H + (int64_t)(g0 + m) * ldb + (KS / 2) * kh, H + (int64_t)(g0 + 32 + m) * ldb + (KS / 2) * kh};
+  auto load = [&](WgFrag<MODE>& f, int64_t i) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = *reinterpret_cast<const f32x4*>(G + (int64_t)(f0 + 32 * t + m) * ldb + i8 + 4 * kh);
-        bb[t] = *reinterpret_cast<const f32x4*>(H + (int64_t)(g0 + 32 * t + m) * ldb + i8 + 4 * kh);
+    for (int t = 0; t < 2; ++t) {
+      if constexpr (MODE == kFP32) {
+        f.a[t] = *reinterpret_cast<const f32x4*>(ga[t] + i);
+        f.b[t] = *reinterpret_cast<const f32x4*>(hb[t] + i);
+      } else {
+        f.a[t] = *reinterpret_cast<const bf16x8*>(ga[t] + i);
+        f.b[t] = *reinterpret_cast<const bf16x8*>(hb[t] + i);
       }
+    }
+  };
+  auto mma = [&](const WgFrag<MODE>& f) {
+    if constexpr (MODE == kFP32) {
+      // lane (m, kh) holds samples 4 kh + q of the step; MFMA q pairs samples q and 4 + q
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
           for (int tb = 0; tb < 2; ++tb)
-            acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ta][q], bb[tb][q], acc[ta][tb], 0, 0, 0);
-    }
-  } else {
-    const __bf16* G = static_cast<const __bf16*>(Gv);
-    const __bf16* H = static_cast<const __bf16*>(Hv);
-    for (int64_t i16 = i0; i16 < i1; i16 += 16) {
-      bf16x8 a[2], bb[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = *reinterpret_cast<const bf16x8*>(G + (int64_t)(f0 + 32 * t + m) * ldb + i16 + 8 * kh);
-        bb[t] = *reinterpret_cast<const bf16x8*>(H + (int64_t)(g0 + 32 * t + m) * ldb + i16 + 8 * kh);
-      }
+            acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[ta][q], f.b[tb][q], acc[ta][tb], 0, 0, 0);
+    } else {
 #pragma unroll
       for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb)
-          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ta], bb[tb], acc[ta][tb], 0, 0, 0);
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[ta], f.b[tb], acc[ta][tb], 0, 0, 0);
     }
+  };
+  // rows hold zeros past B up to the next multiple of 64, so whole steps are read
+  WgFrag<MODE> cur, nxt;
+  if (i0 < i1) load(cur, i0);
+  for (int64_t i = i0; i < i1; i += KS) {
+    if (i + KS < i1) load(nxt, i + KS);
+    mma(cur);
+    cur = nxt;
   }
   // C layout: lane (n = lane%32, half h) holds rows 8 (j/4) + 4 h + j%4 of column n
-  float* out = partial + (int64_t)chunk * Wd * Wd;
+  float* out = partial + ((int64_t)job * nchunks + chunk) * Wd * Wd;
 #pragma unroll
   for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
@@ -1325,25 +1355,39 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(const void* __restrict_
       }
 }
 
-__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.f;
-  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * n + i];
-  out[i] = s;
+// out_j[e] = sum over chunks (in index order) of partial[j][chunk][e], 4 elements per thread.
+__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int job = blockIdx.y;
+  if (t >= n) return;
+  const float* p = partial + (int64_t)job * nchunks * n + t;
+  f32x4 s = {0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < nchunks; ++c) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(p + (int64_t)c * n);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += v[u];
+  }
+  float* o = jobs.out[job] + t;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) o[u] = s[u];
 }
 
-hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, int64_t ldb, int64_t B,
-                             float* partial, int nchunks, float* out, hipStream_t s) {
-  const int tiles = (width / 128) * (width / 128);
+hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
+                             int nchunks, hipStream_t s) {
+  if (jobs.n < 1 || jobs.n > kWgMaxJobs || width % 128) return hipErrorInvalidValue;
+  const int ntile = (width / 128) * (width / 128);
+  const int64_t groups = (int64_t)jobs.n * nchunks;
+  const int64_t per_xcd = (groups + 7) / 8;
+  const unsigned grid = (unsigned)(8 * per_xcd * ntile);
   if (mode == kFP32)
-    hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(tiles * nchunks), dim3(256), 0, s, G, H, width, ldb, B, partial);
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, partial);
   else
-    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(tiles * nchunks), dim3(256), 0, s, G, H, width, ldb, B, partial);
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)width * width;
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nchunks, n, out);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n / 4 + 255) / 256), (unsigned)jobs.n), dim3(256), 0, s,
+                     partial, nchunks, n, jobs);
   return hipGetLastError();
 }
 

@@ -162,10 +162,19 @@ hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
 // Training: weight gradients from the dumped H / G (element type = bf16 for the
 // BF16 modes, float for FP32).
 // ----------------------------------------------------------------------------
-// out[f][g] = sum_{i < B} G[f][i] H[g][i] for f, g < width, via split-K partial
-// sums in `partial` (nchunks * width * width floats) reduced in a fixed order.
-hipError_t launch_wgrad_gemm(const void* G, const void* H, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int nchunks, float* out, hipStream_t s);
+// Up to kWgMaxJobs products in one launch: out_j[f][g] = sum_{i < B} G_j[f][i] H_j[g][i]
+// for f, g < width (a multiple of 128), via split-K partial sums in `partial`
+// (n * nchunks * width * width floats) reduced in a fixed order.  Rows of G and H
+// have stride ldb and hold zeros from B up to the next multiple of 64.
+constexpr int kWgMaxJobs = 3;
+struct WgradJobs {
+  const void* G[kWgMaxJobs];
+  const void* H[kWgMaxJobs];
+  float* out[kWgMaxJobs];
+  int n;
+};
+hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
+                             int nchunks, hipStream_t s);
 int wgrad_chunks(int64_t B);
 // For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
 // ldv) and bias[r] = sum_i A[r][i] (out / bias may be NULL), i < B; chunked partial

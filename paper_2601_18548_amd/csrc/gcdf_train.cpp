@@ -127,7 +127,7 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(&tr->dumpH, dump);
   if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
-  const size_t part = std::max((size_t)gcdf::wgrad_chunks(max_batch) * W * W,
+  const size_t part = std::max((size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
                                 (size_t)gcdf::rr_chunks(max_batch) * W * 10);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->partial), part * 4);
   if (e != hipSuccess) {
@@ -207,9 +207,15 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   if (e == hipSuccess) e = gcdf::launch_fused(tr->net, job, true, true, tr->num_cu, s);
   const int nch = gcdf::wgrad_chunks(B);
   const int gmode = bf ? gcdf::kBF16 : gcdf::kFP32;
-  // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4
-  for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::launch_wgrad_gemm(G(l + 1), H(l), W, gmode, tr->ldb, B, tr->partial, nch, grad + o.Wl[l], s);
+  // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4, one launch
+  gcdf::WgradJobs wj{};
+  wj.n = 3;
+  for (int l = 0; l < 3; ++l) {
+    wj.G[l] = G(l + 1);
+    wj.H[l] = H(l);
+    wj.out[l] = grad + o.Wl[l];
+  }
+  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
   // input layer: dW1 = G_1 V^T, db1 = sum G_1 (the partial buffer is free again:
   // each reduction follows the previous one on the stream)
   float* part = tr->partial;
