@@ -320,33 +320,34 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 }
 
 // ----------------------------------------------------------------------------
-// Training: copy the LDS activation tile (hi plane for the BF16 modes) to a
-// feature-major array dst[f][q0 + n] (row stride ldb), zeros for the ragged tail.
-// All threads take part; each writes whole rows of 64 samples.
+// Training: copy the LDS activation tile (hi plane for the BF16 modes) to HBM in
+// the blocked feature-major layout: element (f, i) of a [W x batch] array sits at
+// ((i / S) * W + f) * S + i % S with S = 16 bytes of samples (8 BF16 or 4 FP32),
+// so the 16-byte fragments of consecutive features are adjacent.  Zeros for the
+// ragged tail of the tile.  All threads take part.
 // ----------------------------------------------------------------------------
 template <int W, int MODE>
 __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {
+  (void)ldb;
   for (int f = threadIdx.x; f < W && MODE == kFP32; f += kThreads) {
-    {
-      const float* a = reinterpret_cast<const float*>(act);
-      float* o = static_cast<float*>(dst) + (int64_t)f * ldb + q0;
+    const float* a = reinterpret_cast<const float*>(act);
 #pragma unroll 4
-      for (int n = 0; n < kTileQ; n += 4) {
-        f32x4 v;
+    for (int n = 0; n < kTileQ; n += 4) {
+      f32x4 v;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int nn = n + u;
-          v[u] = nn < nvalid ? a[(((f >> 3) * kTileQ + nn) * 2 + (f & 1)) * 4 + ((f & 7) >> 1)] : 0.f;
-        }
-        *reinterpret_cast<f32x4*>(o + n) = v;
+      for (int u = 0; u < 4; ++u) {
+        const int nn = n + u;
+        v[u] = nn < nvalid ? a[(((f >> 3) * kTileQ + nn) * 2 + (f & 1)) * 4 + ((f & 7) >> 1)] : 0.f;
       }
+      float* o = static_cast<float*>(dst) + (((q0 + n) >> 2) * W + f) * 4;
+      *reinterpret_cast<f32x4*>(o) = v;
     }
   }
   if constexpr (MODE != kFP32) {
     // The hi plane holds, for each group of 8 features and each query n, the 8
     // features' values as one 16-byte word.  A thread reads the 8x8 block of 8
-    // consecutive queries, transposes it in registers and writes 8 feature rows of
-    // 8 queries (16 bytes each).
+    // consecutive queries, transposes it in registers and writes the 8 features'
+    // 16-byte pieces of that query block.
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const char* a = act;
     constexpr int NG = W / 8;  // feature groups
@@ -367,7 +368,7 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
           const uint32_t x0 = m[2 * jj][fl >> 1], x1 = m[2 * jj + 1][fl >> 1];
           row[jj] = (fl & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
         }
-        __bf16* o = static_cast<__bf16*>(dst) + (int64_t)(8 * g8 + fl) * ldb + q0 + nb * 8;
+        __bf16* o = static_cast<__bf16*>(dst) + (((q0 >> 3) + nb) * W + 8 * g8 + fl) * 8;
         *reinterpret_cast<u32x4*>(o) = row;
       }
     }
@@ -1247,8 +1248,8 @@ hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want
 // ----------------------------------------------------------------------------
 // Training: weight gradients.
 //
-// out[f][g] = sum_i G[f][i] H[g][i] over the batch, G and H feature-major with
-// row stride ldb.  Workgroup (tile, chunk) computes a 128 x 128 block of out over
+// out[f][g] = sum_i G[f][i] H[g][i] over the batch, G and H in the blocked
+// feature-major layout of dump_tile.  Workgroup (tile, chunk) computes a 128 x 128 block of out over
 // one chunk of the batch with matrix cores (4 waves, 64 x 64 each) into
 // partial[chunk]; a second kernel adds the chunks in index order, so the result
 // does not depend on scheduling.
@@ -1301,17 +1302,23 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
   constexpr int KS = MODE == kFP32 ? 8 : 16;  // samples per step
   const E* G = static_cast<const E*>(jobs.G[job]);
   const E* H = static_cast<const E*>(jobs.H[job]);
-  const E* ga[2] = {G + (int64_t)(f0 + m) * ldb + (KS / 2) * kh, G + (int64_t)(f0 + 32 + m) * ldb + (KS / 2) * kh};
-  const E* hb[2] = {H + (int64_t)(g0 + m) * ldb + (KS / 2) * kh, H + (int64_t)(g0 + 32 + m) * ldb + (KS / 2) * kh};
-  auto load = [&](WgFrag<MODE>& f, int64_t i) {
+  // The 16-byte block of S samples of feature f starts at element ((i / S) W + f) S:
+  // lane (m, kh) of a step reads block i / S + kh of its row, and the 32 lanes of
+  // a half read 32 consecutive features, 512 contiguous bytes.
+  constexpr int S = MODE == kFP32 ? 4 : 8;  // samples per 16-byte block (KS = 2 S)
+  constexpr int U = 4;                      // steps per prefetch group
+  const E* ga[2] = {G + (int64_t)(kh * Wd + f0 + m) * S, G + (int64_t)(kh * Wd + f0 + 32 + m) * S};
+  const E* hb[2] = {H + (int64_t)(kh * Wd + g0 + m) * S, H + (int64_t)(kh * Wd + g0 + 32 + m) * S};
+  auto load = [&](WgFrag<MODE>& f, int64_t i, int u) {
+    const int64_t off = ((i + (int64_t)KS * u) / S) * Wd * S;  // first block of step u
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       if constexpr (MODE == kFP32) {
-        f.a[t] = *reinterpret_cast<const f32x4*>(ga[t] + i);
-        f.b[t] = *reinterpret_cast<const f32x4*>(hb[t] + i);
+        f.a[t] = *reinterpret_cast<const f32x4*>(ga[t] + off);
+        f.b[t] = *reinterpret_cast<const f32x4*>(hb[t] + off);
       } else {
-        f.a[t] = *reinterpret_cast<const bf16x8*>(ga[t] + i);
-        f.b[t] = *reinterpret_cast<const bf16x8*>(hb[t] + i);
+        f.a[t] = *reinterpret_cast<const bf16x8*>(ga[t] + off);
+        f.b[t] = *reinterpret_cast<const bf16x8*>(hb[t] + off);
       }
     }
   };
@@ -1333,13 +1340,24 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[ta], f.b[tb], acc[ta][tb], 0, 0, 0);
     }
   };
-  // rows hold zeros past B up to the next multiple of 64, so whole steps are read
-  WgFrag<MODE> cur, nxt;
-  if (i0 < i1) load(cur, i0);
-  for (int64_t i = i0; i < i1; i += KS) {
-    if (i + KS < i1) load(nxt, i + KS);
-    mma(cur);
-    cur = nxt;
+  // Rows hold zeros from B up to the next multiple of 64 and chunks start at
+  // multiples of 64, so whole groups are read.  Double-buffered: the loads of the
+  // next group are in flight while this one runs on the matrix cores.
+  static_assert(U * KS <= kTileQ, "a group must not run past the zero-padded tail");
+  WgFrag<MODE> cur[U], nxt[U];
+  if (i0 < i1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(cur[u], i0, u);
+  }
+  for (int64_t i = i0; i < i1; i += U * KS) {
+    if (i + U * KS < i1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) load(nxt[u], i + U * KS, u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) mma(cur[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }
   // C layout: lane (n = lane%32, half h) holds rows 8 (j/4) + 4 h + j%4 of column n
   float* out = partial + ((int64_t)job * nchunks + chunk) * Wd * Wd;
@@ -1391,92 +1409,78 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
   return hipGetLastError();
 }
 
-// Row reductions over the batch in two fixed-order passes.  Pass 1: grid (row
-// quad, chunk of kRrChunk samples); wave w of a workgroup takes one row, each lane
-// 8 consecutive samples per step (one 16-byte load of A), and the wave's sums go
-// to partial[chunk][row][c] after a butterfly reduction.  Pass 2 adds the chunks
-// in index order.  The result does not depend on scheduling.
-constexpr int kRrChunk = 4096;
+// Row reductions over the batch in two fixed-order passes, A in the blocked
+// feature-major layout of dump_tile.  Pass 1: grid (256-row group, chunk of
+// kRrChunk samples); a thread owns one row and walks the chunk's 16-byte blocks
+// in order (a workgroup reads 4 KB contiguous per block), V is read uniformly.
+// Pass 2 adds the chunks in index order.  The result does not depend on scheduling.
+constexpr int kRrChunk = 512;
 constexpr int kRrMaxC = 9;
 
 int rr_chunks(int64_t B) { return (int)((B + kRrChunk - 1) / kRrChunk); }
 
 template <bool BF>
-__device__ __forceinline__ float rr_load(const void* A, int64_t idx) {
-  if constexpr (BF) return (float)static_cast<const __bf16*>(A)[idx];
-  else return static_cast<const float*>(A)[idx];
-}
-
-template <bool BF>
-__global__ __launch_bounds__(256) void rr_partial_kernel(const void* __restrict__ Av, int64_t lda, int rows, int64_t B,
+__global__ __launch_bounds__(256) void rr_partial_kernel(const void* __restrict__ Av, int rows, int64_t B,
                                                           const float* __restrict__ V, int64_t ldv, int C,
                                                           float* __restrict__ partial) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = blockIdx.x * 4 + wave;
-  if (r >= rows) return;
+  constexpr int S = BF ? 8 : 4;  // samples per 16-byte block
+  __shared__ float sv[kRrMaxC][kRrChunk];  // this chunk of V (zero past B)
+  const int r = blockIdx.x * 256 + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * kRrChunk;
   const int64_t i1 = i0 + kRrChunk < B ? i0 + kRrChunk : B;
+  for (int c = 0; c < C; ++c)
+    for (int k = threadIdx.x; k < kRrChunk; k += 256) sv[c][k] = i0 + k < i1 ? V[(int64_t)c * ldv + i0 + k] : 0.f;
+  __syncthreads();
+  if (r >= rows) return;
   float acc[kRrMaxC + 1];
 #pragma unroll
   for (int c = 0; c <= kRrMaxC; ++c) acc[c] = 0.f;
-  const int64_t arow = (int64_t)r * lda;
-  for (int64_t i = i0 + lane * 8; i < i1; i += 64 * 8) {
-    float a[8];
-    if (i + 8 <= i1) {
+  // NB blocks per round: their loads are issued together, then consumed in order
+  constexpr int NB = 8;
+  static_assert(NB * S <= kTileQ && kRrChunk % (NB * S) == 0, "rounds must stay in the zero-padded tail");
+  typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
+  for (int64_t i = i0; i < i1; i += NB * S) {
+    float a[NB][S];
+    // A round covers NB * S (64 or 32) samples from a multiple of that size below B,
+    // so it stays inside the zero-padded tail (rows are zero from B to the next
+    // multiple of 64): the loads need no condition and are issued together.
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int64_t blk = (((i + k * S) / S) * rows + r) * S;
       if constexpr (BF) {
-        typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
-        const v8 x = *reinterpret_cast<const v8*>(static_cast<const __bf16*>(Av) + arow + i);
+        const v8 x = *reinterpret_cast<const v8*>(static_cast<const __bf16*>(Av) + blk);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = (float)x[u];
+        for (int u = 0; u < S; ++u) a[k][u] = (float)x[u];
       } else {
-        const f32x4 x0 = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + arow + i);
-        const f32x4 x1 = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + arow + i + 4);
+        const f32x4 x = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + blk);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u] = x0[u];
-          a[4 + u] = x1[u];
-        }
+        for (int u = 0; u < S; ++u) a[k][u] = x[u];
       }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = i + u < i1 ? rr_load<BF>(Av, arow + i + u) : 0.f;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[kRrMaxC] += a[u];
-    const bool full = i + 8 <= i1;
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+      for (int u = 0; u < S; ++u) acc[kRrMaxC] += a[k][u];
+    // V from LDS: every lane reads the same word (a broadcast)
+    const int j0 = (int)(i - i0);
     for (int c = 0; c < C; ++c) {
-      const float* v = V + (int64_t)c * ldv + i;
-      float vv[8];
-      if (full && ldv) {  // rows of V start 32-byte aligned (ldv a multiple of 64)
-        const f32x4 v0 = *reinterpret_cast<const f32x4*>(v);
-        const f32x4 v1 = *reinterpret_cast<const f32x4*>(v + 4);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          vv[u] = v0[u];
-          vv[4 + u] = v1[u];
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = i + u < i1 ? v[u] : 0.f;
-      }
       float t = acc[c];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t += a[u] * vv[u];
+      for (int k = 0; k < NB; ++k) {
+        const f32x4* vp = reinterpret_cast<const f32x4*>(&sv[c][j0 + k * S]);
+#pragma unroll
+        for (int h = 0; h < S / 4; ++h) {
+          const f32x4 vv = vp[h];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) t += a[k][4 * h + u] * vv[u];
+        }
+      }
       acc[c] = t;
     }
   }
+  float* out = partial + ((int64_t)blockIdx.y * rows + r) * (kRrMaxC + 1);
 #pragma unroll
-  for (int c = 0; c <= kRrMaxC; ++c) {
-    float t = acc[c];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
-    acc[c] = t;
-  }
-  if (lane == 0) {
-    float* out = partial + ((int64_t)blockIdx.y * rows + r) * (kRrMaxC + 1);
-#pragma unroll
-    for (int c = 0; c <= kRrMaxC; ++c) out[c] = acc[c];
-  }
+  for (int c = 0; c <= kRrMaxC; ++c) out[c] = acc[c];
 }
 
 __global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, int rows, int C, float* __restrict__ out,
@@ -1485,6 +1489,7 @@ __global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, in
   const int r = (int)(t / (kRrMaxC + 1)), c = (int)(t % (kRrMaxC + 1));
   if (r >= rows || (c >= C && c != kRrMaxC)) return;
   float s = 0.f;
+#pragma unroll 8
   for (int k = 0; k < nchunks; ++k) s += partial[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
   if (c == kRrMaxC) {
     if (bias) bias[r] = s;
@@ -1493,20 +1498,40 @@ __global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, in
   }
 }
 
-hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
-                             int64_t ldv, int C, float* out, float* bias, float* partial, hipStream_t s) {
+// One workgroup: out = sum_{i < n} x[i], strided per thread then a fixed tree.
+__global__ __launch_bounds__(256) void vec_sum_kernel(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
+  __shared__ float red[256];
+  float s = 0.f;
+#pragma unroll 8
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
+                             float* out, float* bias, float* partial, hipStream_t s) {
   if (C > kRrMaxC || rows <= 0 || B <= 0) return hipErrorInvalidValue;
   const int nch = rr_chunks(B);
-  const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)nch);
+  const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nch);
   if (a_is_bf16)
-    hipLaunchKernelGGL(rr_partial_kernel<true>, grid, dim3(256), 0, s, A, lda, rows, B, V, ldv, C, partial);
+    hipLaunchKernelGGL(rr_partial_kernel<true>, grid, dim3(256), 0, s, A, rows, B, V, ldv, C, partial);
   else
-    hipLaunchKernelGGL(rr_partial_kernel<false>, grid, dim3(256), 0, s, A, lda, rows, B, V, ldv, C, partial);
+    hipLaunchKernelGGL(rr_partial_kernel<false>, grid, dim3(256), 0, s, A, rows, B, V, ldv, C, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)rows * (kRrMaxC + 1);
   hipLaunchKernelGGL(rr_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nch, rows, C, out,
                      bias);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(vec_sum_kernel, dim3(1), dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
 

@@ -54,9 +54,11 @@ struct Job {
   float* J;                  // dense: [K][Np][9]; pairs: [npairs][9] (nullable)
   unsigned long long* minkey;// dense only: [K] ordered (distance, index) keys (nullable)
   // training (pairs mode): the reverse sweep is seeded with seed[i] = dL/dd_i instead
-  // of 1, and the tile's layer inputs and back-propagated gradients are written
-  // feature-major: dumpH[l][f][i] = h_{l+1}, dumpG[l][f][i] = dL/dz_{l+1} (l = 0..3),
-  // dumpV[c][i] = network input c (FP32); row stride ldb (a multiple of 64).
+  // of 1, and the tile's layer inputs h_{l+1} (dumpH[l]) and back-propagated
+  // gradients dL/dz_{l+1} (dumpG[l]), l = 0..3, are written as [W x ldb] arrays in
+  // the blocked feature-major layout (element (f, i) at ((i / S) W + f) S + i % S,
+  // S = 16 bytes of samples); dumpV[c][i] = network input c (FP32), row stride ldb
+  // (a multiple of 64).
   const float* seed;
   void* dumpH;
   void* dumpG;
@@ -177,11 +179,15 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
                              int nchunks, hipStream_t s);
 int wgrad_chunks(int64_t B);
 // For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
-// ldv) and bias[r] = sum_i A[r][i] (out / bias may be NULL), i < B; chunked partial
-// sums in `partial` (rr_chunks(B) * rows * 10 floats) added in a fixed order.
+// ldv, V[c] holding at least B entries) and bias[r] = sum_i A[r][i] (out / bias may be
+// NULL), i < B, with A (rows x batch) in the blocked feature-major layout of the
+// training dumps; chunked partial sums in `partial` (rr_chunks(B) * rows * 10 floats)
+// added in a fixed order.
 int rr_chunks(int64_t B);
-hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int64_t lda, int rows, int64_t B, const float* V,
-                             int64_t ldv, int C, float* out, float* bias, float* partial, hipStream_t s);
+hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
+                             float* out, float* bias, float* partial, hipStream_t s);
+// *out = sum_{i < n} x[i] in a fixed order (one workgroup).
+hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s);
 
 // Adam step over n floats (see gcdf_adam_step).
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

@@ -4,7 +4,7 @@
 //           packed on the device from the FP32 master copy at every call;
 // backward: the same kernel in training mode -- forward recomputed per tile,
 //           reverse sweep seeded with dL/dd_i, layer inputs h_l and gradients
-//           g_l = dL/dz_l written feature-major -- then
+//           g_l = dL/dz_l written in a blocked feature-major layout -- then
 //             dW_l = G_l H_{l-1}^T       (matrix cores, split-K, fixed-order sum),
 //             dW_1 = G_1 V^T, db_l = sum_i G_l, dw_out = H_4 seed, db_out = sum seed
 //           (fixed-order row reductions).
@@ -220,14 +220,12 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   // each reduction follows the previous one on the stream)
   float* part = tr->partial;
   if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(G(0), bf, tr->ldb, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, part, s);
+    e = gcdf::launch_row_reduce(G(0), bf, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, part, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::launch_row_reduce(G(l + 1), bf, tr->ldb, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], part, s);
+    e = gcdf::launch_row_reduce(G(l + 1), bf, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], part, s);
   // output layer: dw_out = H_4 seed, db_out = sum seed
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(H(3), bf, tr->ldb, W, B, grad_d, 0, 1, grad + o.w5, nullptr, part, s);
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(grad_d, false, 0, 1, B, nullptr, 0, 0, nullptr, grad + o.b5, part, s);
+  if (e == hipSuccess) e = gcdf::launch_row_reduce(H(3), bf, W, B, grad_d, 0, 1, grad + o.w5, nullptr, part, s);
+  if (e == hipSuccess) e = gcdf::launch_vec_sum(grad_d, B, grad + o.b5, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
 }
 
