@@ -57,6 +57,8 @@ def _load():
     lib.gcdf_ref_eval_grad_f64.restype = ctypes.c_int
     lib.gcdf_ref_eval_pairs.argtypes = [P, ctypes.c_size_t, P, P, P, P, I64, P, P, ctypes.c_int]
     lib.gcdf_ref_eval_pairs.restype = ctypes.c_int
+    lib.gcdf_ref_table1_grad.argtypes = [P, ctypes.c_size_t, P, P, P, P, P, P, I64, P, P]
+    lib.gcdf_ref_table1_grad.restype = ctypes.c_double
     lib.gcdf_ref_knot_min.argtypes = [P, I64, I64, P, P]
     lib.gcdf_ref_knot_min.restype = None
     lib.gcdf_ref_mse_grad.argtypes = [P, ctypes.c_size_t, P, P, P, I64, P]
@@ -210,3 +212,40 @@ def mse_grad(blob: bytes, knots, points, y):
         out.append(g[off:off + c].reshape(s))
         off += c
     return loss, out
+
+
+LAMBDA_PAPER = (5.0, 0.1, 0.01, 0.01)  # loss weights of Sec. V-A
+
+
+def table1_grad(blob: bytes, knots, points, fstar, Jstar, m_diag, lam=LAMBDA_PAPER):
+    """Table I training loss over samples (knot i, point i) and its weight gradient.
+
+    Returns (total, [L_dist, L_grad, L_eikonal, L_tension], grads) with grads
+    shaped like the weight arrays, float64.
+    """
+    k, p = _f64(knots, 9), _f64(points, 3)
+    n = len(k)
+    fs = np.ascontiguousarray(fstar, dtype=np.float64)
+    Js = _f64(Jstar, 9)
+    m = np.ascontiguousarray(m_diag, dtype=np.float64)
+    lm = np.ascontiguousarray(lam, dtype=np.float64)
+    assert len(p) == n and fs.shape == (n,) and Js.shape == (n, 9) and m.shape == (9,) and lm.shape == (4,)
+    width, depth = struct.unpack("<2I", blob[12:20])
+    dims = [9] + [width] * depth + [1]
+    shapes = []
+    for li in range(depth + 1):
+        shapes += [(dims[li + 1], dims[li]), (dims[li + 1],)]
+    total_n = sum(int(np.prod(s)) for s in shapes)
+    g = np.empty(total_n, np.float64)
+    losses = np.empty(4, np.float64)
+    b = ctypes.create_string_buffer(blob, len(blob))
+    total = _load().gcdf_ref_table1_grad(b, len(blob), _ptr(k), _ptr(p), _ptr(fs), _ptr(Js), _ptr(m), _ptr(lm), n,
+                                         _ptr(losses), _ptr(g))
+    if np.isnan(total):
+        raise ValueError("oracle rejected the weight blob")
+    out, off = [], 0
+    for s in shapes:
+        c = int(np.prod(s))
+        out.append(g[off:off + c].reshape(s))
+        off += c
+    return total, losses, out

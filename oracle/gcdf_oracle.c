@@ -345,3 +345,169 @@ double gcdf_ref_mse_grad(const void* blob, size_t bytes, const double* knots, co
     free(t);
     return loss;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Training loss of Table I (Sec. III-C) and its weight gradient.            */
+/*                                                                          */
+/* Per sample i with prediction f, configuration gradient J = dF/dq (the    */
+/* query's chain rule) and targets f*, J*:                                   */
+/*   L_dist    = (f - f*)^2                                                  */
+/*   L_grad    = (1 - cos(J, J*))^2                                          */
+/*   L_eikonal = (|J|_{M^-1} - 1)^2,  |J|_{M^-1} = sqrt(sum_c J_c^2 / m_c)   */
+/*   L_tension = |J|^2                                                       */
+/* each averaged over the samples; total = sum_k lambda_k L_k (eq. total_lo, */
+/* weights of Sec. V-A).  The eikonal and tension terms act on the          */
+/* prediction (the table's hat convention is read as "prediction").         */
+/*                                                                          */
+/* Gradient: the loss depends on the weights through f and through          */
+/* J = A e, e = d f / d v (A: the chain rule, independent of the weights).  */
+/* With fbar = dL/df and u = A^T dL/dJ, dL/dW = fbar df/dW + d(u . e)/dW,   */
+/* and u . e is the forward-mode derivative of f along the input direction   */
+/* u.  So: forward, reverse for e, tangent pass along u, then reverse mode  */
+/* through the primal and the tangent program together:                     */
+/*   hbar_L = fbar w_out,  tbar_L = w_out                                     */
+/*   per layer: zdot_bar = tbar * s'(z) (= the reverse sweep's g),           */
+/*              zbar = hbar * s'(z) + tbar * s''(z) * zdot,                  */
+/*              dW += zbar h_prev^T + zdot_bar hdot_prev^T, db += zbar,      */
+/*              hbar_prev = W^T zbar, tbar_prev = W^T zdot_bar;              */
+/*   input layer: dW_1 += zbar v^T + zdot_bar u^T, db_1 += zbar.             */
+/* s = SiLU, s'' = sigma (1 - sigma) (2 + z (1 - 2 sigma)).                 */
+/* ------------------------------------------------------------------------ */
+static double silu_second(double z) {
+    double s = sigmoid(z);
+    return s * (1.0 - s) * (2.0 + z * (1.0 - 2.0 * s));
+}
+
+double gcdf_ref_table1_grad(const void* blob, size_t bytes, const double* knots, const double* points,
+                            const double* fstar, const double* Jstar, const double* m_diag, const double* lambda,
+                            int64_t n, double* losses, double* grad) {
+    net_t net;
+    if (parse_blob(blob, bytes, &net)) return NAN;
+    const int W = net.width, L = net.depth;
+    size_t off_m[16], off_b[16], total = 0;
+    for (int l = 0; l <= L; ++l) {
+        int fi = (l == 0) ? IN_DIM : W;
+        int fo = (l == L) ? 1 : W;
+        off_m[l] = total;
+        total += (size_t)fo * fi;
+        off_b[l] = total;
+        total += (size_t)fo;
+    }
+    memset(grad, 0, sizeof(double) * total);
+    for (int k = 0; k < 4; ++k) losses[k] = 0.0;
+    /* per layer (1..L, stored 0-based): z, h, zdot, hdot, g (= zdot_bar), r (= tbar) */
+    double* z = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* h = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* zd = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* hd = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* g = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* r = (double*)malloc(sizeof(double) * (size_t)W * L);
+    double* hbar = (double*)malloc(sizeof(double) * W);
+    double* zbar = (double*)malloc(sizeof(double) * W);
+    const double inv_n = 1.0 / (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* q = knots + 9 * i;
+        double v[IN_DIM];
+        to_base_frame(q, points + 3 * i, v);
+        for (int c = 3; c < IN_DIM; ++c) v[c] = q[c];
+        /* forward */
+        for (int l = 0; l < L; ++l) {
+            const int fi = (l == 0) ? IN_DIM : W;
+            const double* in = (l == 0) ? v : h + (size_t)(l - 1) * W;
+            for (int o = 0; o < W; ++o) {
+                double acc = net.bias[l][o];
+                for (int c = 0; c < fi; ++c) acc += (double)net.mat[l][(size_t)o * fi + c] * in[c];
+                z[(size_t)l * W + o] = acc;
+                h[(size_t)l * W + o] = silu(acc);
+            }
+        }
+        double f = net.bias[L][0];
+        for (int c = 0; c < W; ++c) f += (double)net.mat[L][c] * h[(size_t)(L - 1) * W + c];
+        /* reverse for e = df/dv: r_L = w_out, g_l = r_l * s'(z_l), r_{l-1} = W_l^T g_l */
+        for (int c = 0; c < W; ++c) r[(size_t)(L - 1) * W + c] = (double)net.mat[L][c];
+        for (int l = L - 1; l >= 0; --l) {
+            for (int c = 0; c < W; ++c) g[(size_t)l * W + c] = r[(size_t)l * W + c] * silu_prime(z[(size_t)l * W + c]);
+            if (l == 0) break;
+            for (int c = 0; c < W; ++c) {
+                double acc = 0.0;
+                for (int o = 0; o < W; ++o) acc += (double)net.mat[l][(size_t)o * W + c] * g[(size_t)l * W + o];
+                r[(size_t)(l - 1) * W + c] = acc;
+            }
+        }
+        double e[IN_DIM], J[IN_DIM];
+        for (int c = 0; c < IN_DIM; ++c) {
+            double acc = 0.0;
+            for (int o = 0; o < W; ++o) acc += (double)net.mat[0][(size_t)o * IN_DIM + c] * g[o];
+            e[c] = acc;
+        }
+        chain_rule(q, v, e, J);
+        /* losses and their derivatives in f and J */
+        const double* Js = Jstar + 9 * i;
+        double nJ2 = 0.0, nJs2 = 0.0, dot = 0.0, nm2 = 0.0;
+        for (int c = 0; c < IN_DIM; ++c) {
+            nJ2 += J[c] * J[c];
+            nJs2 += Js[c] * Js[c];
+            dot += J[c] * Js[c];
+            nm2 += J[c] * J[c] / m_diag[c];
+        }
+        const double nJ = sqrt(nJ2), nJs = sqrt(nJs2), nm = sqrt(nm2);
+        const double cosv = dot / (nJ * nJs);
+        const double rd = f - fstar[i];
+        losses[0] += rd * rd * inv_n;
+        losses[1] += (1.0 - cosv) * (1.0 - cosv) * inv_n;
+        losses[2] += (nm - 1.0) * (nm - 1.0) * inv_n;
+        losses[3] += nJ2 * inv_n;
+        const double fbar = lambda[0] * 2.0 * rd * inv_n;
+        double Jbar[IN_DIM];
+        for (int c = 0; c < IN_DIM; ++c) {
+            const double dcos = Js[c] / (nJ * nJs) - cosv * J[c] / nJ2;
+            Jbar[c] = inv_n * (lambda[1] * (-2.0 * (1.0 - cosv) * dcos) +
+                               lambda[2] * (2.0 * (nm - 1.0) * J[c] / (m_diag[c] * nm)) + lambda[3] * 2.0 * J[c]);
+        }
+        /* u = A^T Jbar (transpose of the chain rule) */
+        const double cy = cos(q[2]), sy = sin(q[2]);
+        double u[IN_DIM];
+        u[0] = -cy * Jbar[0] - sy * Jbar[1] + v[1] * Jbar[2];
+        u[1] = sy * Jbar[0] - cy * Jbar[1] - v[0] * Jbar[2];
+        u[2] = 0.0;
+        for (int c = 3; c < IN_DIM; ++c) u[c] = Jbar[c];
+        /* tangent pass along u */
+        for (int l = 0; l < L; ++l) {
+            const int fi = (l == 0) ? IN_DIM : W;
+            const double* in = (l == 0) ? u : hd + (size_t)(l - 1) * W;
+            for (int o = 0; o < W; ++o) {
+                double acc = 0.0;
+                for (int c = 0; c < fi; ++c) acc += (double)net.mat[l][(size_t)o * fi + c] * in[c];
+                zd[(size_t)l * W + o] = acc;
+                hd[(size_t)l * W + o] = silu_prime(z[(size_t)l * W + o]) * acc;
+            }
+        }
+        /* reverse through primal and tangent; seeds fbar (for f) and 1 (for u . e) */
+        grad[off_b[L]] += fbar;
+        for (int c = 0; c < W; ++c) {
+            grad[off_m[L] + c] += fbar * h[(size_t)(L - 1) * W + c] + hd[(size_t)(L - 1) * W + c];
+            hbar[c] = fbar * (double)net.mat[L][c];
+        }
+        for (int l = L - 1; l >= 0; --l) {
+            const double* zl = z + (size_t)l * W;
+            for (int c = 0; c < W; ++c)
+                zbar[c] = hbar[c] * silu_prime(zl[c]) + r[(size_t)l * W + c] * silu_second(zl[c]) * zd[(size_t)l * W + c];
+            const double* gl = g + (size_t)l * W; /* zdot_bar */
+            const int fi = (l == 0) ? IN_DIM : W;
+            const double* hin = (l == 0) ? v : h + (size_t)(l - 1) * W;
+            const double* hdin = (l == 0) ? u : hd + (size_t)(l - 1) * W;
+            for (int o = 0; o < W; ++o) {
+                grad[off_b[l] + o] += zbar[o];
+                for (int c = 0; c < fi; ++c) grad[off_m[l] + (size_t)o * fi + c] += zbar[o] * hin[c] + gl[o] * hdin[c];
+            }
+            if (l == 0) break;
+            for (int c = 0; c < W; ++c) {
+                double acc = 0.0;
+                for (int o = 0; o < W; ++o) acc += (double)net.mat[l][(size_t)o * W + c] * zbar[o];
+                hbar[c] = acc;
+            }
+        }
+    }
+    free(z); free(h); free(zd); free(hd); free(g); free(r); free(hbar); free(zbar);
+    return lambda[0] * losses[0] + lambda[1] * losses[1] + lambda[2] * losses[2] + lambda[3] * losses[3];
+}
