@@ -16,7 +16,8 @@ Prints one JSON line: pairs (queries) per second, plus
   serving      : p50 / p99 latency of a Poisson request trace through gcdf_submit;
   constraints  : partitions around a 128-knot trajectory, the CSR query, the
                  Jacobian pattern and the single-step projection (HBM roofline);
-  training     : steps/s of the width-256 training step (batch 65,536, Adam).
+  training     : steps/s of the width-256 training step (batch 65,536, Adam);
+  training_table1: the same with the paper's four-term Table I loss (FP32).
 """
 from __future__ import annotations
 
@@ -247,6 +248,53 @@ def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int =
             "loss_first": float(loss0.item()) if loss0 is not None else None, "loss_last": float(loss.item())}
 
 
+def table1_bench(g, torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
+    """Training step on the paper's Table I loss (value, direction, weighted eikonal,
+    tension; weights of Sec. V-A), FP32, targets = a seeded teacher's distances and
+    configuration gradients, Adam: gcdf_train_table1 + gcdf_adam_step."""
+    from paper_2601_18548_amd import train
+    from paper_2601_18548_amd import workloads as wl
+
+    teacher = wl.weights(width, seed=601, bf16_hidden=False)
+    student = wl.weights(width, seed=602, bf16_hidden=False)
+    k, p, noise = wl.training_batch(batch, 603)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    tr = train.Trainer(width, "fp32", max_batch=batch)
+    # targets: the teacher's distance and configuration gradient per sample, from a CSR
+    # query with one row per knot (knot i, point i) (+ N(0, 1e-3) noise on the value)
+    ctx = g.Context(teacher.to_blob(), width, "fp32")
+    d = torch.empty(batch, device="cuda")
+    J = torch.empty((batch, 9), device="cuda")
+    idx = torch.arange(batch, dtype=torch.int64, device="cuda")
+    off = torch.arange(batch + 1, dtype=torch.int64, device="cuda")
+    ctx.eval_grad_csr(kt, pt, off, idx.to(torch.int32), c=d, J=J)
+    ctx.close()
+    fstar = (d + torch.from_numpy(noise).cuda()).contiguous()
+    m_diag = [4.0, 4.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0]
+    params = train.flat_params(student).requires_grad_(True)
+    opt = train.Adam(params, lr=1e-3)
+    first = None
+    for _ in range(warmup):
+        losses, gr = tr.table1(params.detach(), kt, pt, fstar, J, m_diag)
+        params.grad = gr
+        opt.step()
+        first = float(losses[4]) if first is None else first
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        losses, gr = tr.table1(params.detach(), kt, pt, fstar, J, m_diag)
+        params.grad = gr
+        opt.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # algorithmic work per sample: 12 W x W products in the loss pass (forward, reverse,
+    # tangent, adjoint) + 6 in the weight gradients + the query for J (6)
+    fl = 24 * width * width * batch
+    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "batch": batch, "width": width,
+            "precision": "fp32", "loss": "Table I, lambda = (5, 0.1, 0.01, 0.01), M = diag(4, 4, 1, ..., 1)",
+            "tflops_algorithmic": fl * steps / el / 1e12, "loss_first": first, "loss_last": float(losses[4])}
+
+
 def cpu_baseline(wk, seconds: float):
     import numpy as np
 
@@ -374,6 +422,10 @@ def main():
     if args.train_steps > 0:
         out["training"] = train_bench(torch, args.train_steps, 3)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
+    if args.train_steps > 0:
+        out["training_table1"] = table1_bench(g, torch, max(5, args.train_steps // 4), 2)
+        print("bench: Table I training %.3f ms/step" % out["training_table1"]["ms_per_step"], file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wk, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -268,6 +268,23 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
                                 int64_t B, const float* grad_d, float* grad_params, int32_t reuse_packed,
                                 void* stream);
 
+/* The training loss of Table I (Sec. III-C) over the samples (knot i, point i)
+ * and its weight gradient.  With F the network distance and J = dF/dq the
+ * configuration gradient of the query (chain rule through the base frame):
+ *   L_dist = mean (F - fstar)^2,  L_grad = mean (1 - cos(J, Jstar))^2,
+ *   L_eikonal = mean (|J|_{M^-1} - 1)^2,  L_tension = mean |J|^2,
+ * total = sum_k lambda[k] L_k (lambda = (5, 0.1, 0.01, 0.01) in Sec. V-A).
+ * fstar float32[B], Jstar float32[B][9] (device); m_diag (9 weights of M) and
+ * lambda (4) are HOST float arrays.  losses: device float32[5] = the four terms
+ * and the total; grad_params (device, overwritten) = d total / d params.  The
+ * gradient is exact reverse mode through the query and its Jacobian (a tangent
+ * pass along A^T dL/dJ, then the adjoint of both programs), deterministic.  FP32
+ * trainers only (EINVAL otherwise); the first call allocates a workspace of about
+ * 16 W max_batch floats plus per-CU scratch (ENOMEM if that fails). */
+gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                              int64_t B, const float* fstar, const float* Jstar, const float* m_diag,
+                              const float* lambda, float* losses, float* grad_params, void* stream);
+
 /* One Adam step (the optimiser of the paper's training, Sec. V-A) over n device
  * floats, in torch.optim.Adam's arithmetic (no weight decay, no amsgrad):
  *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;

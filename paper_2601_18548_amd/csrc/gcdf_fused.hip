@@ -856,6 +856,391 @@ __global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, c
 }
 
 // ----------------------------------------------------------------------------
+// Table I training loss: per tile of 64 samples (sample i = knot i, point i)
+//   forward      z_l, h_l                       (3 GEMMs W_l)
+//   reverse      r_l = W_{l+1}^T g_{l+1}, g_l = r_l s'(z_l), r_4 = w_out    (3 GEMMs W^T)
+//   tangent      zdot_1 = W_1 u, hdot_l = s'(z_l) zdot_l, zdot_{l+1} = W hdot (3 GEMMs W_l)
+//   adjoint      zbar_4 = fbar w_out s'(z_4) + w_out s''(z_4) zdot_4,
+//                zbar_l = hbar_l s'(z_l) + r_l s''(z_l) zdot_l, hbar_l = W^T zbar (3 GEMMs W^T)
+// The weight gradient is then sum_i zbar_l h_{l-1}^T + g_l hdot_{l-1}^T per layer (and
+// the input / output layers' equivalents), formed from the dumps by the GEMM and
+// reduction kernels.  Pre-activations z, zdot and the products r are kept per
+// workgroup in a register-order scratch (float4 k of thread t at (k * 256 + t) * 4),
+// and every elementwise step streams them group by group, so at most one
+// accumulator array is live.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void silu_d12(float z, float& d1, float& d2) {
+  const float t = __builtin_amdgcn_exp2f(-z * kLog2e);
+  const float sg = __builtin_amdgcn_rcpf(1.0f + t);
+  const float om = 1.0f - sg;
+  d1 = sg + z * sg * om;                       // s'
+  d2 = sg * om * (2.0f + z * (1.0f - 2.0f * sg));  // s''
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads, 1) void table1_tiles(const DevNet net, const T1Job job, int64_t ntiles) {
+  constexpr int MODE = kFP32;
+  using G = Geo<W>;
+  constexpr int MT = G::MT;
+  constexpr int XF = G::XIN_FLOATS;
+  __shared__ __attribute__((aligned(16))) char lds[G::LDS_BYTES];
+  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
+  const Lane<W, MODE>& ln = tc.ln;
+  const Bases<W, MODE>& b = tc.b;
+  float* uin = tc.red;  // [64][9] tangent direction of the tile's samples
+  const int tid = threadIdx.x;
+  const size_t arr = (size_t)kThreads * 64;
+  float* scr = job.scratch + (size_t)blockIdx.x * kT1ScratchArrays * arr;
+  float* sZ = scr;             // z_1..z_4
+  float* sZd = scr + 4 * arr;  // zdot_1..zdot_4
+  float* sR = scr + 8 * arr;   // r_1..r_3
+  const size_t layer = (size_t)W * job.ldb;
+  // float4 idx of this thread in a scratch array (elements 4 (idx % 4) .. +3 of
+  // accumulator (i, nt) with idx / 4 = i * 2 + nt)
+  auto sget = [&](const float* base, int idx) {
+    return *reinterpret_cast<const f32x4*>(base + ((size_t)idx * kThreads + tid) * 4);
+  };
+  auto sput = [&](float* base, int idx, const f32x4& v) {
+    *reinterpret_cast<f32x4*>(base + ((size_t)idx * kThreads + tid) * 4) = v;
+  };
+  auto zero = [&](f32x16 (&x)[MT][2]) {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[i][nt][j] = 0.f;
+  };
+  // a (accumulators) -> LDS tile, element by element through f(I, NT, j, value, z, zd, r),
+  // with z / zd / r read from the scratch arrays when given (group by group)
+  auto emit = [&](f32x16 (&a)[MT][2], const float* bz, const float* bzd, const float* br, auto&& f) {
+    static_for<MT>([&](auto I) {
+      static_for<2>([&](auto GP) {
+        static_for<2>([&](auto NT) {
+          float v[8];
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int idx = (I * 2 + NT) * 4 + 2 * GP + hh;
+            const f32x4 zz = bz ? sget(bz, idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+            const f32x4 dd = bzd ? sget(bzd, idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+            const f32x4 rr = br ? sget(br, idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int j = 8 * GP + 4 * hh + u;
+              v[4 * hh + u] = f(I, NT, j, a[I][NT][j], zz[u], dd[u], rr[u]);
+            }
+          }
+          act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    });
+  };
+  auto put_all = [&](float* base, const f32x16 (&x)[MT][2]) {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          sput(base, (i * 2 + nt) * 4 + k,
+               f32x4{x[i][nt][4 * k], x[i][nt][4 * k + 1], x[i][nt][4 * k + 2], x[i][nt][4 * k + 3]});
+  };
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t q0 = tile * kTileQ;
+    const int nvalid = (int)(job.B - q0 < kTileQ ? job.B - q0 : kTileQ);
+    auto dumpl = [&](float* arrbase, int l) { dump_tile<W, MODE>(tc.act, arrbase + l * layer, job.ldb, q0, nvalid); };
+    // ---- prologue: base-frame points, fbar and u of the tile's samples ----
+    if (tid < kTileQ) {
+      const int64_t q = q0 + tid;
+      const bool ok = q < job.B;
+      const int64_t qc = ok ? q : job.B - 1;
+      const float* kn = job.knots + qc * kInDim;
+      const float* pt = job.points + qc * 3;
+      float sn, cs;
+      sincosf(kn[2], &sn, &cs);
+      const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
+      float* x = tc.xin + tid * XF;
+      x[0] = cs * ux + sn * uy;
+      x[1] = -sn * ux + cs * uy;
+      x[2] = pt[2];
+      x[3] = cs;
+      x[4] = sn;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
+      x[11] = ok ? job.fbar[qc] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) uin[tid * 9 + c] = ok ? job.u[c * job.ldb + qc] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) job.V[c * job.ldb + q] = ok ? x[c] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) job.V[(3 + c) * job.ldb + q] = ok ? x[5 + c] : 0.f;
+    }
+    __syncthreads();
+
+    // ---- input layer: z_1 to the scratch, h_1 to LDS (8 rows at a time) ----
+    static_for<MT>([&](auto I) {
+      static_for<2>([&](auto GP) {
+        f32x4 wa[8], wb[8];
+        f32x2 wc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float* w = b.w1 + (16 * I + 8 * GP + q) * 12;
+          wa[q] = *reinterpret_cast<const f32x4*>(w);
+          wb[q] = *reinterpret_cast<const f32x4*>(w + 4);
+          wc[q] = *reinterpret_cast<const f32x2*>(w + 8);
+        }
+        static_for<2>([&](auto NT) {
+          const float* x = b.xin + NT * 32 * XF;
+          float zv[8], hv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float c = arm_term(wa[q][3], wb[q][0], wb[q][1], wb[q][2], wb[q][3], wc[q][0], wc[q][1], x + 5);
+            zv[q] = input_preact(c, wa[q][0], wa[q][1], wa[q][2], x);
+            hv[q] = silu_only(zv[q]);
+          }
+          const int idx = (I * 2 + NT) * 4 + 2 * GP;
+          sput(sZ, idx, f32x4{zv[0], zv[1], zv[2], zv[3]});
+          sput(sZ, idx + 1, f32x4{zv[4], zv[5], zv[6], zv[7]});
+          act_store_pair<W, MODE, I, GP, NT>(ln, hv);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    });
+    __syncthreads();
+    dumpl(job.H, 0);
+
+    f32x16 a[MT][2];
+    // ---- hidden layers forward: z to the scratch, h to LDS ----
+    static_for<3>([&](auto L) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 b4 = *reinterpret_cast<const f32x4*>(b.bh + L * W + 16 * i + 4 * g);
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[i][nt][4 * g + r] = b4[r];
+        }
+      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+      __syncthreads();
+      put_all(sZ + (L + 1) * arr, a);
+      emit(a, nullptr, nullptr, nullptr, [&](int, int, int, float acc, float, float, float) { return silu_only(acc); });
+      __syncthreads();
+      dumpl(job.H, L + 1);
+      __syncthreads();
+    });
+    // ---- reverse sweep: g_4 = w_out s'(z_4); r_l = W_{l+1}^T g_{l+1}; g_l = r_l s'(z_l) ----
+    emit(a, sZ + 3 * arr, nullptr, nullptr, [&](int I, int, int j, float, float z, float, float) {
+      float d1, d2;
+      silu_d12(z, d1, d2);
+      return b.w5[16 * I + j] * d1;
+    });
+    __syncthreads();
+    dumpl(job.G, 3);
+    static_for<3>([&](auto LL) {
+      constexpr int L = 2 - LL;  // W_{L+2}^T g_{L+2} = r_{L+1}
+      zero(a);
+      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+      __syncthreads();
+      put_all(sR + L * arr, a);
+      emit(a, sZ + L * arr, nullptr, nullptr, [&](int, int, int, float acc, float z, float, float) {
+        float d1, d2;
+        silu_d12(z, d1, d2);
+        return acc * d1;
+      });
+      __syncthreads();
+      dumpl(job.G, L);
+      __syncthreads();
+    });
+    // ---- tangent pass along u: zdot_1 = W_1 u to the scratch, hdot_1 to LDS ----
+    static_for<MT>([&](auto I) {
+      static_for<2>([&](auto GP) {
+        f32x4 wa[8], wb[8];
+        f32x2 wc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float* w = b.w1 + (16 * I + 8 * GP + q) * 12;
+          wa[q] = *reinterpret_cast<const f32x4*>(w);
+          wb[q] = *reinterpret_cast<const f32x4*>(w + 4);
+          wc[q] = *reinterpret_cast<const f32x2*>(w + 8);
+        }
+        static_for<2>([&](auto NT) {
+          const float* uu = uin + (32 * NT + ln.n0) * 9;
+          const int idx = (I * 2 + NT) * 4 + 2 * GP;
+          const f32x4 z0 = sget(sZ, idx), z1 = sget(sZ, idx + 1);
+          float zd[8], hd[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float t = wa[q][0] * uu[0];
+            t += wa[q][1] * uu[1];
+            t += wa[q][2] * uu[2];
+            t += wb[q][0] * uu[3];
+            t += wb[q][1] * uu[4];
+            t += wb[q][2] * uu[5];
+            t += wb[q][3] * uu[6];
+            t += wc[q][0] * uu[7];
+            t += wc[q][1] * uu[8];
+            zd[q] = t;
+            float d1, d2;
+            silu_d12(q < 4 ? z0[q] : z1[q - 4], d1, d2);
+            hd[q] = d1 * t;
+          }
+          sput(sZd, idx, f32x4{zd[0], zd[1], zd[2], zd[3]});
+          sput(sZd, idx + 1, f32x4{zd[4], zd[5], zd[6], zd[7]});
+          act_store_pair<W, MODE, I, GP, NT>(ln, hd);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    });
+    __syncthreads();
+    dumpl(job.Hd, 0);
+    static_for<3>([&](auto L) {
+      // zdot_{L+2} = W_{L+2} hdot_{L+1}; hdot_{L+2} = s'(z_{L+2}) zdot_{L+2}
+      zero(a);
+      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+      __syncthreads();
+      put_all(sZd + (L + 1) * arr, a);
+      emit(a, sZ + (L + 1) * arr, nullptr, nullptr, [&](int, int, int, float acc, float z, float, float) {
+        float d1, d2;
+        silu_d12(z, d1, d2);
+        return d1 * acc;
+      });
+      __syncthreads();
+      dumpl(job.Hd, L + 1);
+      __syncthreads();
+    });
+    // ---- adjoint of the primal ----
+    emit(a, sZ + 3 * arr, sZd + 3 * arr, nullptr, [&](int I, int NT, int j, float, float z, float zd, float) {
+      const float w5 = b.w5[16 * I + j];
+      const float fb = b.xin[NT * 32 * XF + 11];
+      float d1, d2;
+      silu_d12(z, d1, d2);
+      return (fb * w5) * d1 + w5 * d2 * zd;
+    });
+    __syncthreads();
+    dumpl(job.Zb, 3);
+    static_for<3>([&](auto LL) {
+      constexpr int L = 2 - LL;  // hbar_{L+1} = W_{L+2}^T zbar_{L+2}
+      zero(a);
+      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+      __syncthreads();
+      emit(a, sZ + L * arr, sZd + L * arr, sR + L * arr, [&](int, int, int, float hb, float z, float zd, float r) {
+        float d1, d2;
+        silu_d12(z, d1, d2);
+        return hb * d1 + r * d2 * zd;
+      });
+      __syncthreads();
+      dumpl(job.Zb, L);
+      __syncthreads();
+    });
+  }
+}
+
+hipError_t launch_table1_tiles(const DevNet& net, const T1Job& job, int grid, hipStream_t s) {
+  if (net.width != 256 || net.mode != kFP32) return hipErrorInvalidValue;
+  const int64_t ntiles = (job.B + kTileQ - 1) / kTileQ;
+  hipLaunchKernelGGL(table1_tiles<256>, dim3((unsigned)grid), dim3(kThreads), 0, s, net, job, ntiles);
+  return hipGetLastError();
+}
+
+// Per sample: loss terms and their derivatives (fixed-order sums over the batch).
+__global__ __launch_bounds__(256) void table1_loss_kernel(const float* __restrict__ knots,
+                                                          const float* __restrict__ points, const float* __restrict__ d,
+                                                          const float* __restrict__ J, const float* __restrict__ fstar,
+                                                          const float* __restrict__ Jstar, Minv9 mdiag, f32x4 lam,
+                                                          int64_t B, int64_t ldb, float* __restrict__ fbar,
+                                                          float* __restrict__ u, float* __restrict__ part) {
+  __shared__ float red[4][256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float l4[4] = {0.f, 0.f, 0.f, 0.f};
+  const float invn = 1.0f / (float)B;
+  if (i < ldb) {
+    float uu[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float fb = 0.f;
+    if (i < B) {
+      const float* Ji = J + i * 9;
+      const float* Js = Jstar + i * 9;
+      float nJ2 = 0.f, nJs2 = 0.f, dot = 0.f, nm2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        nJ2 += Ji[c] * Ji[c];
+        nJs2 += Js[c] * Js[c];
+        dot += Ji[c] * Js[c];
+        nm2 += Ji[c] * Ji[c] / mdiag.v[c];
+      }
+      const float nJ = sqrtf(nJ2), nJs = sqrtf(nJs2), nm = sqrtf(nm2);
+      const float cosv = dot / (nJ * nJs);
+      const float rd = d[i] - fstar[i];
+      l4[0] = rd * rd * invn;
+      l4[1] = (1.f - cosv) * (1.f - cosv) * invn;
+      l4[2] = (nm - 1.f) * (nm - 1.f) * invn;
+      l4[3] = nJ2 * invn;
+      fb = lam[0] * 2.f * rd * invn;
+      float Jb[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const float dcos = Js[c] / (nJ * nJs) - cosv * Ji[c] / nJ2;
+        Jb[c] = invn * (lam[1] * (-2.f * (1.f - cosv) * dcos) + lam[2] * (2.f * (nm - 1.f) * Ji[c] / (mdiag.v[c] * nm)) +
+                        lam[3] * 2.f * Ji[c]);
+      }
+      const float* kn = knots + i * 9;
+      const float* pt = points + i * 3;
+      float sn, cs;
+      sincosf(kn[2], &sn, &cs);
+      const float ux = pt[0] - kn[0], uy = pt[1] - kn[1];
+      const float px = cs * ux + sn * uy, py = -sn * ux + cs * uy;
+      uu[0] = -cs * Jb[0] - sn * Jb[1] + py * Jb[2];
+      uu[1] = sn * Jb[0] - cs * Jb[1] - px * Jb[2];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) uu[c] = Jb[c];
+      fbar[i] = fb;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) u[c * ldb + i] = uu[c];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = l4[k];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void table1_loss_sum_kernel(const float* __restrict__ part, int nblocks, f32x4 lam, float* __restrict__ losses) {
+  if (threadIdx.x != 0) return;
+  float t[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < nblocks; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] += part[k * 4 + c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) losses[c] = t[c];
+  losses[4] = lam[0] * t[0] + lam[1] * t[1] + lam[2] * t[2] + lam[3] * t[3];
+}
+
+hipError_t launch_table1_loss(const float* knots, const float* points, const float* d, const float* J,
+                              const float* fstar, const float* Jstar, const float* m_diag, const float* lambda,
+                              int64_t B, int64_t ldb, float* fbar, float* u, float* part, float* losses,
+                              hipStream_t s) {
+  Minv9 md{};
+  for (int c = 0; c < 9; ++c) md.v[c] = m_diag[c];
+  const f32x4 lam = {lambda[0], lambda[1], lambda[2], lambda[3]};
+  const int nb = (int)((ldb + 255) / 256);
+  hipLaunchKernelGGL(table1_loss_kernel, dim3((unsigned)nb), dim3(256), 0, s, knots, points, d, J, fstar, Jstar, md,
+                     lam, B, ldb, fbar, u, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(table1_loss_sum_kernel, dim3(1), dim3(64), 0, s, part, nb, lam, losses);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
 // Persistent serving kernel.  Requests are published by the host in sequence
 // order into ServeCtl (pinned host memory); every workgroup walks the sequence
 // with its own cursor and claims tiles with a compare-and-swap on the slot's
@@ -1374,7 +1759,7 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
 }
 
 // out_j[e] = sum over chunks (in index order) of partial[j][chunk][e], 4 elements per thread.
-__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs) {
+__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs, int accum) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   const int job = blockIdx.y;
   if (t >= n) return;
@@ -1387,11 +1772,11 @@ __global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks
   }
   float* o = jobs.out[job] + t;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) o[u] = s[u];
+  for (int u = 0; u < 4; ++u) o[u] = accum ? o[u] + s[u] : s[u];
 }
 
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int nchunks, hipStream_t s) {
+                             int nchunks, hipStream_t s, bool accumulate) {
   if (jobs.n < 1 || jobs.n > kWgMaxJobs || width % 128) return hipErrorInvalidValue;
   const int ntile = (width / 128) * (width / 128);
   const int64_t groups = (int64_t)jobs.n * nchunks;
@@ -1405,7 +1790,7 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)width * width;
   hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n / 4 + 255) / 256), (unsigned)jobs.n), dim3(256), 0, s,
-                     partial, nchunks, n, jobs);
+                     partial, nchunks, n, jobs, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1484,7 +1869,7 @@ __global__ __launch_bounds__(256) void rr_partial_kernel(const void* __restrict_
 }
 
 __global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, int rows, int C, float* __restrict__ out,
-                              float* __restrict__ bias) {
+                              float* __restrict__ bias, int accum) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = (int)(t / (kRrMaxC + 1)), c = (int)(t % (kRrMaxC + 1));
   if (r >= rows || (c >= C && c != kRrMaxC)) return;
@@ -1492,9 +1877,9 @@ __global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, in
 #pragma unroll 8
   for (int k = 0; k < nchunks; ++k) s += partial[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
   if (c == kRrMaxC) {
-    if (bias) bias[r] = s;
+    if (bias) bias[r] = accum ? bias[r] + s : s;
   } else if (out) {
-    out[(int64_t)r * C + c] = s;
+    out[(int64_t)r * C + c] = accum ? out[(int64_t)r * C + c] + s : s;
   }
 }
 
@@ -1514,7 +1899,7 @@ __global__ __launch_bounds__(256) void vec_sum_kernel(const float* __restrict__ 
 }
 
 hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
-                             float* out, float* bias, float* partial, hipStream_t s) {
+                             float* out, float* bias, float* partial, hipStream_t s, bool accumulate) {
   if (C > kRrMaxC || rows <= 0 || B <= 0) return hipErrorInvalidValue;
   const int nch = rr_chunks(B);
   const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nch);
@@ -1526,7 +1911,7 @@ hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B,
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)rows * (kRrMaxC + 1);
   hipLaunchKernelGGL(rr_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nch, rows, C, out,
-                     bias);
+                     bias, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -176,7 +176,7 @@ struct WgradJobs {
   int n;
 };
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int nchunks, hipStream_t s);
+                             int nchunks, hipStream_t s, bool accumulate = false);
 int wgrad_chunks(int64_t B);
 // For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
 // ldv, V[c] holding at least B entries) and bias[r] = sum_i A[r][i] (out / bias may be
@@ -185,9 +185,40 @@ int wgrad_chunks(int64_t B);
 // added in a fixed order.
 int rr_chunks(int64_t B);
 hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
-                             float* out, float* bias, float* partial, hipStream_t s);
+                             float* out, float* bias, float* partial, hipStream_t s, bool accumulate = false);
 // *out = sum_{i < n} x[i] in a fixed order (one workgroup).
 hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s);
+
+// Table I training loss (width 256, FP32): per 64-sample tile, the forward, the
+// reverse sweep for e = dF/dv, the tangent pass along u and the reverse mode through
+// both programs (see table1_tiles).  Dumps (blocked feature-major, [W x ldb] each):
+//   H[l] = h_{l+1}, G[l] = g_{l+1} (reverse sweep, = d/dz of the tangent output),
+//   Hd[l] = hdot_{l+1} (tangent), Zb[l] = zbar_{l+1} (adjoint of the primal), l = 0..3;
+// V[c][i] = network input c.  scratch: per workgroup of the grid, 11 arrays of
+// kThreads * 64 floats (pre-activations, tangent pre-activations, reverse products).
+struct T1Job {
+  const float* knots;
+  const float* points;
+  int64_t B, ldb;
+  const float* fbar;  // [B] dL/dF per sample
+  const float* u;     // [9][ldb] A^T dL/dJ per sample (input-space tangent direction)
+  float* H;
+  float* G;
+  float* Hd;
+  float* Zb;
+  float* V;
+  float* scratch;
+};
+constexpr int kT1ScratchArrays = 11;
+hipError_t launch_table1_tiles(const DevNet& net, const T1Job& job, int grid, hipStream_t s);
+// Per-sample loss terms and their derivatives: from d[i], J[i][9] (the query), targets
+// fstar, Jstar, m_diag (9) and lambda (4): fbar[i] = dL/dd_i, u[c][i] (row stride ldb,
+// zero from B to ldb), and losses[0..3] = the four averaged terms, losses[4] = total,
+// summed in a fixed order (part: 4 * ceil(ldb / 256) floats of scratch).
+hipError_t launch_table1_loss(const float* knots, const float* points, const float* d, const float* J,
+                              const float* fstar, const float* Jstar, const float* m_diag, const float* lambda,
+                              int64_t B, int64_t ldb, float* fbar, float* u, float* part, float* losses,
+                              hipStream_t s);
 
 // Adam step over n floats (see gcdf_adam_step).
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

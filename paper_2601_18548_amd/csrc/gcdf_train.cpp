@@ -31,6 +31,9 @@ struct gcdf_trainer {
   float* dumpV = nullptr;
   float* partial = nullptr;
   const float* packed_from = nullptr;  // params pointer of the last packing
+  // Table I loss workspace (allocated at its first use)
+  float* t1 = nullptr;  // d, J, fbar, u, partial sums, Hd, Zb, per-workgroup scratch
+  size_t t1_bytes = 0;
 };
 
 namespace {
@@ -156,6 +159,7 @@ void gcdf_trainer_destroy(gcdf_trainer* tr) {
   (void)hipFree(tr->dumpG);
   (void)hipFree(tr->dumpV);
   (void)hipFree(tr->partial);
+  (void)hipFree(tr->t1);
   delete tr;
 }
 
@@ -227,6 +231,107 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   if (e == hipSuccess) e = gcdf::launch_row_reduce(H(3), bf, W, B, grad_d, 0, 1, grad + o.w5, nullptr, part, s);
   if (e == hipSuccess) e = gcdf::launch_vec_sum(grad_d, B, grad + o.b5, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
+}
+
+gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
+                              int64_t B, const float* fstar, const float* Jstar, const float* m_diag,
+                              const float* lambda, float* losses, float* grad, void* stream) {
+  gcdf_status st = check(tr, params, knots, points, B);
+  if (st != GCDF_OK) return st;
+  if (!fstar || !Jstar || !m_diag || !lambda || !losses || !grad)
+    return tfail(GCDF_EINVAL, "NULL argument to gcdf_train_table1");
+  if (tr->mode != GCDF_FP32) return tfail(GCDF_EINVAL, "the Table I loss is built for a GCDF_FP32 trainer");
+  for (int c = 0; c < 9; ++c)
+    if (!(m_diag[c] > 0.f) || !std::isfinite(m_diag[c])) return tfail(GCDF_EINVAL, "m_diag must be finite and > 0");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(lambda[k])) return tfail(GCDF_EINVAL, "lambda must be finite");
+  DevGuard g(tr->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = tr->W;
+  const int64_t ldb = tr->ldb;
+  const size_t layer = (size_t)W * ldb;
+  const int grid = tr->num_cu;
+  const size_t arr = (size_t)gcdf::kThreads * 64;
+  // workspace: d [ldb], J [9 ldb], fbar [ldb], u [9 ldb], part [4 ceil(ldb/256)], Hd, Zb [4 layer each],
+  // scratch [grid * 11 * arr]
+  const size_t n_d = ldb, n_J = 9 * ldb, n_f = ldb, n_u = 9 * ldb, n_p = 4 * ((ldb + 255) / 256) + 8;
+  const size_t n_dump = 4 * layer, n_s = (size_t)grid * gcdf::kT1ScratchArrays * arr;
+  const size_t need = 4 * (n_d + n_J + n_f + n_u + n_p + 2 * n_dump + n_s);
+  if (!tr->t1) {
+    if (hipMalloc(reinterpret_cast<void**>(&tr->t1), need) != hipSuccess) {
+      tr->t1 = nullptr;
+      return tfail(GCDF_ENOMEM, "Table I workspace allocation (%zu bytes) failed", need);
+    }
+    tr->t1_bytes = need;
+  }
+  float* d = tr->t1;
+  float* J = d + n_d;
+  float* fbar = J + n_J;
+  float* u = fbar + n_f;
+  float* part = u + n_u;
+  float* Hd = part + n_p;
+  float* Zb = Hd + n_dump;
+  float* scratch = Zb + n_dump;
+  float* H = static_cast<float*>(tr->dumpH);
+  float* Gs = static_cast<float*>(tr->dumpG);
+  const Offsets o(W);
+  hipError_t e = pack(tr, params, s);
+  // 1. the query over the samples: d and J
+  gcdf::Job qj{};
+  qj.knots = knots;
+  qj.points = points;
+  qj.K = B;
+  qj.Np = B;
+  qj.npairs = B;
+  qj.d = d;
+  qj.J = J;
+  if (e == hipSuccess) e = gcdf::launch_fused(tr->net, qj, true, true, tr->num_cu, s);
+  // 2. loss terms, dL/dF and u = A^T dL/dJ per sample
+  if (e == hipSuccess)
+    e = gcdf::launch_table1_loss(knots, points, d, J, fstar, Jstar, m_diag, lambda, B, ldb, fbar, u, part, losses, s);
+  // 3. per tile: forward, reverse, tangent, adjoint (dumps)
+  gcdf::T1Job tj{};
+  tj.knots = knots;
+  tj.points = points;
+  tj.B = B;
+  tj.ldb = ldb;
+  tj.fbar = fbar;
+  tj.u = u;
+  tj.H = H;
+  tj.G = Gs;
+  tj.Hd = Hd;
+  tj.Zb = Zb;
+  tj.V = tr->dumpV;
+  tj.scratch = scratch;
+  const int64_t ntiles = (B + gcdf::kTileQ - 1) / gcdf::kTileQ;
+  if (e == hipSuccess) e = gcdf::launch_table1_tiles(tr->net, tj, (int)std::min<int64_t>(grid, ntiles), s);
+  // 4. dW_l = sum zbar_l h_{l-1}^T + g_l hdot_{l-1}^T for the hidden layers
+  const int nch = gcdf::wgrad_chunks(B);
+  gcdf::WgradJobs a{}, b{};
+  a.n = b.n = 3;
+  for (int l = 0; l < 3; ++l) {
+    a.G[l] = Zb + (l + 1) * layer;
+    a.H[l] = H + l * layer;
+    b.G[l] = Gs + (l + 1) * layer;
+    b.H[l] = Hd + l * layer;
+    a.out[l] = b.out[l] = grad + o.Wl[l];
+  }
+  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(a, W, gcdf::kFP32, ldb, B, tr->partial, nch, s, false);
+  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(b, W, gcdf::kFP32, ldb, B, tr->partial, nch, s, true);
+  // 5. input layer: dW_1 = sum zbar_1 v^T + g_1 u^T, db_1 = sum zbar_1; db_l = sum zbar_l
+  float* rp = tr->partial;
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(Zb, false, W, B, tr->dumpV, ldb, 9, grad + o.W1, grad + o.b1, rp, s, false);
+  if (e == hipSuccess) e = gcdf::launch_row_reduce(Gs, false, W, B, u, ldb, 9, grad + o.W1, nullptr, rp, s, true);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l)
+    e = gcdf::launch_row_reduce(Zb + (l + 1) * layer, false, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], rp, s, false);
+  // 6. output layer: dw_out = sum fbar h_4 + hdot_4, db_out = sum fbar
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(H + 3 * layer, false, W, B, fbar, ldb, 1, grad + o.w5, nullptr, rp, s, false);
+  if (e == hipSuccess)
+    e = gcdf::launch_row_reduce(Hd + 3 * layer, false, W, B, nullptr, 0, 0, nullptr, grad + o.w5, rp, s, true);
+  if (e == hipSuccess) e = gcdf::launch_vec_sum(fbar, B, grad + o.b5, s);
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_table1: %s", hipGetErrorString(e));
 }
 
 gcdf_status gcdf_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,

@@ -80,6 +80,26 @@ class Trainer:
         return grad
 
 
+    LAMBDA_PAPER = (5.0, 0.1, 0.01, 0.01)  # loss weights of Sec. V-A
+
+    def table1(self, params, knots, points, fstar, Jstar, m_diag, lam=LAMBDA_PAPER, grad=None, stream=None):
+        """Table I loss (4 terms + total, device float32[5]) and its weight gradient."""
+        import torch
+
+        B = knots.shape[0]
+        if grad is None:
+            grad = torch.empty_like(params)
+        losses = torch.empty(5, dtype=torch.float32, device=params.device)
+        m = (ctypes.c_float * 9)(*[float(v) for v in m_diag])
+        lm = (ctypes.c_float * 4)(*[float(v) for v in lam])
+        self._packed = None
+        _check(library().gcdf_train_table1(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
+                                           fstar.data_ptr(), Jstar.data_ptr(), m, lm, losses.data_ptr(),
+                                           grad.data_ptr(), _stream(stream)))
+        self._packed = (params, params._version)
+        return losses, grad
+
+
 def _checked(t, dtype_name):
     import torch
 
