@@ -104,7 +104,7 @@ struct Geo {
   static constexpr int NKB = W / 16;                 // 16-deep K blocks (bf16)
   static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
   static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
-  static constexpr int XIN_FLOATS = 16;              // per query: p'(3), cos, sin, arm(6), pad
+  static constexpr int XIN_FLOATS = 17;              // per query: p'(3), cos, sin, arm(6), seed, pad; odd stride: lanes reading one field of 32 queries hit 32 different banks
   static constexpr int RED_VALS = 10;                // d + 9 input-gradient components
   static constexpr int LDS_BYTES =
       ACT_BYTES + kTileQ * XIN_FLOATS * 4 + W * 4 + kWaves * RED_VALS * kTileQ * 4 + 4 * W * 4;
