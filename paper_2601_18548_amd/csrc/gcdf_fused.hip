@@ -1243,9 +1243,12 @@ hipError_t launch_table1_loss(const float* knots, const float* points, const flo
 // ----------------------------------------------------------------------------
 // Persistent serving kernel.  Requests are published by the host in sequence
 // order into ServeCtl (pinned host memory); every workgroup walks the sequence
-// with its own cursor and claims tiles with a compare-and-swap on the slot's
-// (seq, count) word, so a late workgroup can never claim tiles of a request
-// that has since been replaced in its slot.
+// with its own cursor and claims tiles from the slot's (seq, count) word (a
+// compare-and-swap re-tags it for a new request, a fetch_add hands out the
+// rest), so a late workgroup can never run tiles of a request that has since
+// been replaced in its slot under the wrong descriptor.  The first workgroup
+// that stays idle ends the launch for all (the drain word); tiles not yet
+// claimed then wait in the claim words for the next launch.
 //
 // Memory ordering is paid per request, not per tile: claims are relaxed; a
 // workgroup acquires (system scope) once when it sees new publications; when it
@@ -1264,7 +1267,7 @@ __device__ __forceinline__ T sys_relaxed(const T* p) {
 
 template <int W, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, ServeCtl* ctl, ServeDev* dev,
-                                                          uint64_t first_seq, uint64_t idle_ticks) {
+                                                          uint64_t first_seq, uint64_t idle_ticks, uint32_t epoch) {
   __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
   __shared__ int64_t claim_info[3];  // claimed seq (or -1: exit, -2: none), tile, seq to finalize (or -1)
   __shared__ ServeDesc cur;          // the request this workgroup is working on
@@ -1283,7 +1286,29 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
   while (true) {
     if (tid == 0) {
       int64_t got_seq = -1, got_tile = 0, fin_seq = -1;
+      bool leave = false;
+      // Report the tiles of request cur_seq run here (the caller has established that
+      // no further tile of it will be claimed here); the report that completes the
+      // request makes this workgroup its finalizer.
+      auto report = [&]() {
+        const uint32_t s = (uint32_t)(cur_seq % slots);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this workgroup's stores and atomics
+        const unsigned long long done =
+            __hip_atomic_fetch_add(&dev->done[s], open_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + open_count;
+        open_count = 0;
+        if (done == cur.done_target) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every contributor's results
+          fin = cur;
+          fin_seq = (int64_t)cur_seq;
+        }
+      };
       while (true) {
+        if (__hip_atomic_load(&dev->drain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
+          // another workgroup ended this launch: claim nothing more
+          if (open_count) report();
+          leave = true;
+          break;
+        }
         if (seq >= pub) {
           const uint64_t p = sys_relaxed(&ctl->published);
           if (p > pub) {
@@ -1341,32 +1366,30 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
           }
           if (got_seq >= 0) break;
           if (moved_on) {
-            if (open_count && cur_seq == seq) {
-              // leaving request seq: release this workgroup's stores and atomics, then report
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-              const unsigned long long done =
-                  __hip_atomic_fetch_add(&dev->done[s], open_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                  open_count;
-              open_count = 0;
-              if (done == cur.done_target) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every contributor's results
-                fin = cur;
-                fin_seq = (int64_t)seq;
-              }
-            }
+            if (open_count && cur_seq == seq) report();  // leaving request seq
             ++seq;
             if (fin_seq >= 0) break;
           }
         } else {
-          if (sys_relaxed(&ctl->stop) || __builtin_amdgcn_s_memrealtime() - idle_since > idle_ticks) break;
+          if (sys_relaxed(&ctl->stop)) {
+            leave = true;
+            break;
+          }
+          if (__builtin_amdgcn_s_memrealtime() - idle_since > idle_ticks) {
+            // idle: end the launch for every workgroup
+            __hip_atomic_store(&dev->drain, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (open_count) report();  // (none expected: every published request has been left)
+            leave = true;
+            break;
+          }
           // idle: back off up to ~4 us between polls of host memory
           for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(16);
           backoff = backoff < 8 ? 2 * backoff : 8;
         }
       }
       backoff = 1;
-      // -1: exit (no claimable work), -2: nothing claimed but a request to finalize
-      claim_info[0] = got_seq >= 0 ? got_seq : (fin_seq >= 0 ? -2 : -1);
+      // -1: exit (after finalizing, if fin_seq is set), -2: nothing claimed but a request to finalize
+      claim_info[0] = got_seq >= 0 ? got_seq : (fin_seq >= 0 && !leave ? -2 : -1);
       claim_info[1] = got_tile;
       claim_info[2] = fin_seq;
       if (got_seq >= 0 && (uint64_t)got_seq != cur_seq) {
@@ -1427,24 +1450,25 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
 
 template <int W, int MODE>
 static hipError_t launch_serve_t(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq,
-                                 uint64_t idle_ticks, int num_cu, hipStream_t s) {
-  hipLaunchKernelGGL((serve_loop<W, MODE>), dim3(num_cu), dim3(kThreads), 0, s, net, ctl, dev, first_seq, idle_ticks);
+                                 uint64_t idle_ticks, uint32_t epoch, int num_cu, hipStream_t s) {
+  hipLaunchKernelGGL((serve_loop<W, MODE>), dim3(num_cu), dim3(kThreads), 0, s, net, ctl, dev, first_seq, idle_ticks,
+                     epoch);
   return hipGetLastError();
 }
 
 hipError_t launch_serve(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq, uint64_t idle_ticks,
-                        int num_cu, hipStream_t s) {
+                        uint32_t epoch, int num_cu, hipStream_t s) {
   if (net.width == 256) {
     switch (net.mode) {
-      case kFP32: return launch_serve_t<256, kFP32>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
-      case kBF16: return launch_serve_t<256, kBF16>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
-      default: return launch_serve_t<256, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+      case kFP32: return launch_serve_t<256, kFP32>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+      case kBF16: return launch_serve_t<256, kBF16>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+      default: return launch_serve_t<256, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
     }
   }
   switch (net.mode) {
-    case kFP32: return launch_serve_t<512, kFP32>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
-    case kBF16: return launch_serve_t<512, kBF16>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
-    default: return launch_serve_t<512, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, num_cu, s);
+    case kFP32: return launch_serve_t<512, kFP32>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+    case kBF16: return launch_serve_t<512, kBF16>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+    default: return launch_serve_t<512, kBF16X2>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
   }
 }
 

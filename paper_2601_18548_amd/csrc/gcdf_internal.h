@@ -150,13 +150,18 @@ struct ServeCtl {
 struct ServeDev {
   unsigned long long claim[kMaxSlots];  // (seq << 32) | tiles claimed of request seq
   unsigned long long done[kMaxSlots];   // tiles finished in the slot, cumulative over its requests
+  uint32_t drain;                       // epoch of the launch that is draining (0: none yet)
 };
 
 // Launch the persistent serving kernel; it processes published requests from
-// sequence number first_seq on and returns once `stop` is set or no work has
-// appeared for idle_ticks of the 100 MHz real-time counter.
+// sequence number first_seq on and returns once `stop` is set or a workgroup has
+// found no work for idle_ticks of the 100 MHz real-time counter.  Exit is
+// collective: that workgroup writes `epoch` (non-zero, distinct per launch) into
+// dev->drain, and every workgroup stops claiming at its next claim, reports the
+// tiles it ran and returns, so a launch never lingers with part of its grid.
+// Tiles left unclaimed stay in the claim words for the next launch.
 hipError_t launch_serve(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq, uint64_t idle_ticks,
-                        int num_cu, hipStream_t s);
+                        uint32_t epoch, int num_cu, hipStream_t s);
 
 hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
 

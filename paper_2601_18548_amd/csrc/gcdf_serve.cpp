@@ -7,8 +7,10 @@
 //    one's descriptor into pinned host memory and publishes it;
 //  * the persistent kernel (one workgroup per compute unit) claims tiles of
 //    every published request, so requests that arrive while others run share
-//    the device; it exits after an idle period and the worker relaunches it
-//    when work is pending;
+//    the device; after an idle period the whole grid exits together (a grid
+//    that had lost part of its workgroups would keep serving at a fraction of
+//    the device while new arrivals kept the rest busy) and the worker relaunches
+//    it when work is pending;
 //  * completion is a per-slot sequence number written by the device with a
 //    system-scope release; gcdf_poll and the worker read it.
 #include "gcdf_serve.h"
@@ -102,6 +104,7 @@ struct Server {
   hipStream_t stream = nullptr;
   hipEvent_t kernel_done = nullptr;
   bool kernel_live = false;
+  uint32_t epoch = 0;           // launches so far (the drain word starts at 0)
 
   std::mutex mu;
   std::condition_variable cv;
@@ -191,7 +194,8 @@ struct Server {
       }
     }
     if (running.empty()) return;
-    const hipError_t e = launch_serve(ctx_net(ctx), ctl, dev, lowest_live_seq_locked(), kIdleTicks,
+    if (++epoch == 0) ++epoch;
+    const hipError_t e = launch_serve(ctx_net(ctx), ctl, dev, lowest_live_seq_locked(), kIdleTicks, epoch,
                                       ctx_num_cu(ctx), stream);
     if (e == hipSuccess && hipEventRecord(kernel_done, stream) == hipSuccess) {
       kernel_live = true;
