@@ -7,7 +7,10 @@ and its Python binding) never does, and this package never imports it.
 ``gcdf_oracle.c`` holds the plain double-precision definition of every step
 of the query (base-frame transform, distance MLP, reverse-mode input gradient,
 chain rule to the full configuration, per-knot minimum, and the MSE weight
-gradient used by the training form).  ``toy.py`` holds a brute-force GCDF for
+gradient used by the training form), for point obstacles (network input
+[p', a], 9 wide) and for sphere obstacles (x, y, z, r) with the 10-wide input
+[p', r, a] of the primitive-aware extension (Sec. VII); the blob's in_dim
+selects which.  ``toy.py`` holds a brute-force GCDF for
 a small planar robot, used to test the GCDF structure of Theorem 1.
 """
 from __future__ import annotations
@@ -43,6 +46,8 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
+    lib.gcdf_ref_in_dim.argtypes = [P, ctypes.c_size_t]
+    lib.gcdf_ref_in_dim.restype = ctypes.c_int
     lib.gcdf_ref_threads.argtypes = [ctypes.c_int]
     lib.gcdf_ref_threads.restype = ctypes.c_int
     lib.gcdf_ref_transform.argtypes = [P, P, I64, P]
@@ -108,13 +113,28 @@ def chain(knots, points, e) -> np.ndarray:
     return out
 
 
+def in_dim(blob: bytes) -> int:
+    """Network input width of a weight blob: 9 (points) or 10 (spheres)."""
+    b = ctypes.create_string_buffer(blob, len(blob))
+    n = _load().gcdf_ref_in_dim(b, len(blob))
+    if n < 0:
+        raise ValueError("oracle rejected the weight blob")
+    return n
+
+
+def obstacle_dim(blob: bytes) -> int:
+    """Floats per obstacle for a blob: 3 (x, y, z) or 4 (x, y, z, r)."""
+    return in_dim(blob) - 6
+
+
 def mlp(blob: bytes, v, with_grad: bool = True, nthreads: int = 0):
-    """Network value d (n,) and input gradient e (n, 9) at network inputs v (n, 9)."""
+    """Network value d (n,) and input gradient e (n, in_dim) at network inputs v (n, in_dim)."""
+    ni = in_dim(blob)
     v = np.ascontiguousarray(v, dtype=np.float64)
-    assert v.ndim == 2 and v.shape[1] == 9
+    assert v.ndim == 2 and v.shape[1] == ni
     n = len(v)
     d = np.empty(n, np.float64)
-    e = np.empty((n, 9), np.float64) if with_grad else None
+    e = np.empty((n, ni), np.float64) if with_grad else None
     b = ctypes.create_string_buffer(blob, len(blob))
     rc = _load().gcdf_ref_mlp(b, len(blob), _ptr(v), n, _ptr(d), _ptr(e) if with_grad else None, nthreads)
     if rc:
@@ -125,12 +145,13 @@ def mlp(blob: bytes, v, with_grad: bool = True, nthreads: int = 0):
 def eval_grad(blob: bytes, knots, points, with_grad: bool = True, nthreads: int = 0):
     """All pairs, knot-major: d (K, Np) and J (K, Np, 9) in float64.
 
-    float32 inputs go through the float32 entry point (exact widening);
-    float64 inputs through the double-precision one.
+    points: (Np, 3), or (Np, 4) spheres for a 10-input blob.  float32 inputs
+    go through the float32 entry point (exact widening); float64 inputs
+    through the double-precision one.
     """
     dbl = np.asarray(knots).dtype == np.float64 or np.asarray(points).dtype == np.float64
     conv = _f64 if dbl else _f32
-    k, p = conv(knots, 9), conv(points, 3)
+    k, p = conv(knots, 9), conv(points, obstacle_dim(blob))
     K, Np = len(k), len(p)
     d = np.empty((K, Np), np.float64)
     J = np.empty((K, Np, 9), np.float64) if with_grad else None
@@ -144,7 +165,7 @@ def eval_grad(blob: bytes, knots, points, with_grad: bool = True, nthreads: int 
 
 def eval_pairs(blob: bytes, knots, points, kidx, pidx, with_grad: bool = True, nthreads: int = 0):
     """Selected pairs (knots[kidx[i]], points[pidx[i]]): d (n,), J (n, 9)."""
-    k, p = _f32(knots, 9), _f32(points, 3)
+    k, p = _f32(knots, 9), _f32(points, obstacle_dim(blob))
     ki = np.ascontiguousarray(kidx, dtype=np.int64)
     pi = np.ascontiguousarray(pidx, dtype=np.int64)
     assert ki.shape == pi.shape and ki.ndim == 1

@@ -23,6 +23,10 @@ Readings where the paper is silent or garbled:
   decision is taken in float32 exactly as written, dx*dx + dy*dy <= r*r with
   every operation rounded (no fused multiply-add), points in ascending
   index order inside a partition;
+* sphere obstacles (x, y, z, s) of the primitive-aware extension (Sec. VII):
+  the sphere is in range when it reaches into the disc, i.e. its centre's
+  planar distance is <= radius + s, decided as dx*dx + dy*dy <= t*t with
+  t = radius + s, every operation rounded in float32;
 * the column offset of P_i prints as 2Nn(i-1), which overruns the matrix for
   i >= 2; the state layout x_i in R^{2n} puts q_i at columns 2n(i-1) + 1 ...
   2n(i-1) + n (1-based), which is the offset used here.
@@ -38,14 +42,22 @@ N_CONF = 9  # (x, y, yaw, a1..a6)
 
 def partition(ref_xy, points, radius: float):
     """Brute-force partitions: for each reference base position, the indices of
-    the points whose planar distance to it is within ``radius``.
+    the points whose planar distance to it is within ``radius`` (for spheres,
+    within ``radius`` plus the sphere's radius).
 
-    ref_xy: (N, 2) base positions; points: (M, 3).  Returns (offsets int64
-    (N+1,), idx int32 (sum m_i,)) in CSR form, ascending inside each row.
+    ref_xy: (N, 2) base positions; points: (M, 3), or (M, 4) spheres.  Returns
+    (offsets int64 (N+1,), idx int32 (sum m_i,)) in CSR form, ascending inside
+    each row.
     """
     ref = np.asarray(ref_xy, np.float32).reshape(-1, 2)
-    p = np.asarray(points, np.float32).reshape(-1, 3)
-    r2 = np.float32(radius) * np.float32(radius)
+    p = np.asarray(points, np.float32)
+    if p.ndim != 2 or p.shape[1] not in (3, 4):
+        raise ValueError("points must be (M, 3) or (M, 4)")
+    if p.shape[1] == 4:
+        t = np.float32(radius) + p[:, 3]
+        r2 = t * t  # per sphere, float32
+    else:
+        r2 = np.float32(radius) * np.float32(radius)
     offsets = [0]
     idx = []
     for i in range(len(ref)):

@@ -25,6 +25,13 @@
  *   - per knot, the minimum over points and the lowest index attaining it
  *     (the constraint f - delta >= 0 of eq. optimization-in-general holds
  *     for all points iff it holds for the minimum).
+ *   - the primitive-aware variant of the closing discussion (Sec. VII): the
+ *     obstacle is a sphere (p, r) and the network reads (q, p, r).  Input
+ *     width 10, in the order [p', r, a]: the radius is a property of the
+ *     obstacle, unchanged by the rigid base-frame motion, so it passes
+ *     through the transform, and the configuration gradient is still the
+ *     chain rule through p' alone.  A blob's in_dim (9 or 10) selects the
+ *     variant; obstacles then hold 3 or 4 floats (x, y, z[, r]).
  *
  * Everything is the plain definition: double precision, straight loops, no
  * blocking and no library calls beyond exp().  SiLU(z) = z * s(z) with
@@ -38,28 +45,32 @@
 #include <omp.h>
 #endif
 
-#define IN_DIM 9
+#define IN_DIM 9   /* configuration coordinates (x, y, yaw, a1..a6) */
+#define MAX_IN 10  /* network inputs: 9, or 10 with an obstacle radius */
 
 typedef struct {
+    int in_dim;           /* 9: [p', a];  10: [p', r, a] */
     int width;
     int depth;            /* number of SiLU hidden layers */
     const float* mat[16]; /* mat[l]: out x in, row-major; mat[depth] is the 1 x width output row */
     const float* bias[16];
 } net_t;
 
-/* Parse the little-endian weight blob: "GCDF", version 1, in_dim 9, width,
- * depth, 3 reserved u32, then float32 W1, b1, ..., W_depth, b_depth, w_out, b_out. */
+/* Parse the little-endian weight blob: "GCDF", version 1, in_dim (9 or 10),
+ * width, depth, 3 reserved u32, then float32 W1, b1, ..., W_depth, b_depth,
+ * w_out, b_out. */
 static int parse_blob(const void* blob, size_t bytes, net_t* n) {
     const uint32_t* h = (const uint32_t*)blob;
     if (bytes < 32 || memcmp(blob, "GCDF", 4) != 0) return -1;
-    if (h[1] != 1 || h[2] != IN_DIM) return -1;
+    if (h[1] != 1 || (h[2] != IN_DIM && h[2] != MAX_IN)) return -1;
+    n->in_dim = (int)h[2];
     n->width = (int)h[3];
     n->depth = (int)h[4];
     if (n->width <= 0 || n->depth < 1 || n->depth > 15) return -1;
     const float* f = (const float*)((const char*)blob + 32);
     size_t used = 0;
     for (int l = 0; l <= n->depth; ++l) {
-        int fi = (l == 0) ? IN_DIM : n->width;
+        int fi = (l == 0) ? n->in_dim : n->width;
         int fo = (l == n->depth) ? 1 : n->width;
         n->mat[l] = f + used;
         used += (size_t)fo * fi;
@@ -87,27 +98,37 @@ static void to_base_frame(const double* q, const double* p, double pp[3]) {
     pp[2] = p[2];
 }
 
-/* Chain rule from the network-input gradient e = dd/d[p', a] to the
- * configuration gradient J = dd/d(x, y, yaw, a1..a6).
+/* Chain rule from the network-input gradient e = dd/d[p', (r,) a] (in_dim
+ * entries) to the configuration gradient J = dd/d(x, y, yaw, a1..a6).
  *   dp'x/dx = -c, dp'y/dx =  s;  dp'x/dy = -s, dp'y/dy = -c;
- *   dp'x/dyaw = p'y, dp'y/dyaw = -p'x;  the arm part passes through. */
-static void chain_rule(const double* q, const double pp[3], const double e[IN_DIM], double J[IN_DIM]) {
+ *   dp'x/dyaw = p'y, dp'y/dyaw = -p'x;  the arm part passes through; the
+ *   radius does not depend on the configuration. */
+static void chain_rule(const double* q, const double pp[3], const double* e, int in_dim, double J[IN_DIM]) {
     double c = cos(q[2]), s = sin(q[2]);
     J[0] = -(c * e[0] - s * e[1]);
     J[1] = -(s * e[0] + c * e[1]);
     J[2] = e[0] * pp[1] - e[1] * pp[0];
-    for (int i = 3; i < IN_DIM; ++i) J[i] = e[i];
+    for (int i = 3; i < IN_DIM; ++i) J[i] = e[in_dim - IN_DIM + i];
 }
 
-/* Network value at input v; if e != NULL also dd/dv by reverse mode.
+/* Network input for knot q and obstacle p (x, y, z, and r when in_dim is 10):
+ * v = [p', (r,) a]; pp receives p'. */
+static void network_input(int in_dim, const double* q, const double* p, double* v, double pp[3]) {
+    to_base_frame(q, p, pp);
+    for (int c = 0; c < 3; ++c) v[c] = pp[c];
+    if (in_dim == MAX_IN) v[3] = p[3];
+    for (int c = 3; c < IN_DIM; ++c) v[in_dim - IN_DIM + c] = q[c];
+}
+
+/* Network value at input v (in_dim entries); if e != NULL also dd/dv by reverse mode.
  * z and h must each hold depth*width doubles (pre-activations and SiLU
  * outputs per hidden layer), g and t width doubles each. */
-static double mlp(const net_t* n, const double v[IN_DIM], double* e, double* z, double* h, double* g, double* t) {
-    const int W = n->width, L = n->depth;
+static double mlp(const net_t* n, const double* v, double* e, double* z, double* h, double* g, double* t) {
+    const int W = n->width, L = n->depth, NI = n->in_dim;
     /* forward: z_1 = W_1 v + b_1; z_l = W_l h_{l-1} + b_l; h_l = SiLU(z_l) */
     for (int r = 0; r < W; ++r) {
         double acc = n->bias[0][r];
-        for (int c = 0; c < IN_DIM; ++c) acc += (double)n->mat[0][r * IN_DIM + c] * v[c];
+        for (int c = 0; c < NI; ++c) acc += (double)n->mat[0][r * NI + c] * v[c];
         z[r] = acc;
         h[r] = silu(acc);
     }
@@ -138,9 +159,9 @@ static double mlp(const net_t* n, const double v[IN_DIM], double* e, double* z, 
         }
         memcpy(g, t, sizeof(double) * W);
     }
-    for (int c = 0; c < IN_DIM; ++c) {
+    for (int c = 0; c < NI; ++c) {
         double acc = 0.0;
-        for (int r = 0; r < W; ++r) acc += (double)n->mat[0][r * IN_DIM + c] * g[r];
+        for (int r = 0; r < W; ++r) acc += (double)n->mat[0][r * NI + c] * g[r];
         e[c] = acc;
     }
     return d;
@@ -170,11 +191,17 @@ void gcdf_ref_chain(const double* knots, const double* points, const double* e, 
     for (int64_t i = 0; i < n; ++i) {
         double pp[3];
         to_base_frame(knots + 9 * i, points + 3 * i, pp);
-        chain_rule(knots + 9 * i, pp, e + 9 * i, J + 9 * i);
+        chain_rule(knots + 9 * i, pp, e + 9 * i, IN_DIM, J + 9 * i);
     }
 }
 
-/* Network value (and input gradient if e != NULL) at n inputs v (n x 9). */
+/* Network input width of a blob (9 or 10), or -1 if malformed. */
+int gcdf_ref_in_dim(const void* blob, size_t bytes) {
+    net_t net;
+    return parse_blob(blob, bytes, &net) ? -1 : net.in_dim;
+}
+
+/* Network value (and input gradient if e != NULL) at n inputs v (n x in_dim). */
 int gcdf_ref_mlp(const void* blob, size_t bytes, const double* v, int64_t n, double* d, double* e, int nthreads) {
     net_t net;
     if (parse_blob(blob, bytes, &net)) return -1;
@@ -186,14 +213,15 @@ int gcdf_ref_mlp(const void* blob, size_t bytes, const double* v, int64_t n, dou
         double* g = h + (size_t)W * net.depth;
         double* t = g + W;
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < n; ++i) d[i] = mlp(&net, v + 9 * i, e ? e + 9 * i : NULL, z, h, g, t);
+        for (int64_t i = 0; i < n; ++i)
+            d[i] = mlp(&net, v + (size_t)net.in_dim * i, e ? e + (size_t)net.in_dim * i : NULL, z, h, g, t);
         free(z);
     }
     return 0;
 }
 
-/* All (knot, point) pairs, knot-major: d[k*Np + j], J[(k*Np + j)*9 + c] (J may be NULL).
- * Inputs in double precision. */
+/* All (knot, obstacle) pairs, knot-major: d[k*Np + j], J[(k*Np + j)*9 + c] (J may be NULL).
+ * Inputs in double precision; obstacles hold in_dim - 6 values (x, y, z[, r]). */
 int gcdf_ref_eval_grad_f64(const void* blob, size_t bytes, const double* knots, int64_t K,
                            const double* points, int64_t Np, double* d, double* J, int nthreads) {
     net_t net;
@@ -208,12 +236,11 @@ int gcdf_ref_eval_grad_f64(const void* blob, size_t bytes, const double* knots, 
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < K * Np; ++i) {
             const double* q = knots + 9 * (i / Np);
-            const double* p = points + 3 * (i % Np);
-            double v[IN_DIM], e[IN_DIM];
-            to_base_frame(q, p, v);
-            for (int c = 3; c < IN_DIM; ++c) v[c] = q[c];
+            const double* p = points + (size_t)(net.in_dim - 6) * (i % Np);
+            double v[MAX_IN], e[MAX_IN], pp[3];
+            network_input(net.in_dim, q, p, v, pp);
             d[i] = mlp(&net, v, J ? e : NULL, z, h, g, t);
-            if (J) chain_rule(q, v, e, J + 9 * i);
+            if (J) chain_rule(q, pp, e, net.in_dim, J + 9 * i);
         }
         free(z);
     }
@@ -229,8 +256,10 @@ static double* widen(const float* a, int64_t n) {
 /* Same with the library's float32 inputs, widened exactly to double. */
 int gcdf_ref_eval_grad(const void* blob, size_t bytes, const float* knots, int64_t K,
                        const float* points, int64_t Np, double* d, double* J, int nthreads) {
+    const int in_dim = gcdf_ref_in_dim(blob, bytes);
+    if (in_dim < 0) return -1;
     double* kd = widen(knots, 9 * K);
-    double* pd = widen(points, 3 * Np);
+    double* pd = widen(points, (int64_t)(in_dim - 6) * Np);
     int rc = gcdf_ref_eval_grad_f64(blob, bytes, kd, K, pd, Np, d, J, nthreads);
     free(kd);
     free(pd);
@@ -249,16 +278,16 @@ int gcdf_ref_eval_pairs(const void* blob, size_t bytes, const float* knots, cons
         double* h = z + (size_t)W * net.depth;
         double* g = h + (size_t)W * net.depth;
         double* t = g + W;
+        const int pd = net.in_dim - 6;
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            double q[IN_DIM], p[3];
+            double q[IN_DIM], p[4];
             for (int c = 0; c < IN_DIM; ++c) q[c] = (double)knots[9 * kidx[i] + c];
-            for (int c = 0; c < 3; ++c) p[c] = (double)points[3 * pidx[i] + c];
-            double v[IN_DIM], e[IN_DIM];
-            to_base_frame(q, p, v);
-            for (int c = 3; c < IN_DIM; ++c) v[c] = q[c];
+            for (int c = 0; c < pd; ++c) p[c] = (double)points[pd * pidx[i] + c];
+            double v[MAX_IN], e[MAX_IN], pp[3];
+            network_input(net.in_dim, q, p, v, pp);
             d[i] = mlp(&net, v, J ? e : NULL, z, h, g, t);
-            if (J) chain_rule(q, v, e, J + 9 * i);
+            if (J) chain_rule(q, pp, e, net.in_dim, J + 9 * i);
         }
         free(z);
     }
@@ -285,7 +314,7 @@ void gcdf_ref_knot_min(const double* d, int64_t K, int64_t Np, double* dmin, int
 double gcdf_ref_mse_grad(const void* blob, size_t bytes, const double* knots, const double* points,
                          const double* y, int64_t n, double* grad) {
     net_t net;
-    if (parse_blob(blob, bytes, &net)) return NAN;
+    if (parse_blob(blob, bytes, &net) || net.in_dim != IN_DIM) return NAN;
     const int W = net.width, L = net.depth;
     /* offsets of each parameter array inside grad */
     size_t off_m[16], off_b[16], total = 0;
@@ -382,7 +411,7 @@ double gcdf_ref_table1_grad(const void* blob, size_t bytes, const double* knots,
                             const double* fstar, const double* Jstar, const double* m_diag, const double* lambda,
                             int64_t n, double* losses, double* grad) {
     net_t net;
-    if (parse_blob(blob, bytes, &net)) return NAN;
+    if (parse_blob(blob, bytes, &net) || net.in_dim != IN_DIM) return NAN;
     const int W = net.width, L = net.depth;
     size_t off_m[16], off_b[16], total = 0;
     for (int l = 0; l <= L; ++l) {
@@ -440,7 +469,7 @@ double gcdf_ref_table1_grad(const void* blob, size_t bytes, const double* knots,
             for (int o = 0; o < W; ++o) acc += (double)net.mat[0][(size_t)o * IN_DIM + c] * g[o];
             e[c] = acc;
         }
-        chain_rule(q, v, e, J);
+        chain_rule(q, v, e, IN_DIM, J);
         /* losses and their derivatives in f and J */
         const double* Js = Jstar + 9 * i;
         double nJ2 = 0.0, nJs2 = 0.0, dot = 0.0, nm2 = 0.0;

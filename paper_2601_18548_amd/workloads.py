@@ -12,6 +12,9 @@ arm joints -> ``float32[K][9]`` in the order (x, y, yaw, a1..a6).
 
 Obstacle points are stored as ``float32[Np][3]`` world coordinates, the "one
 array of all obstacle coordinates" of the partition data structure (Sec. IV-A).
+For the primitive-aware network (sphere obstacles with radius r, the (q, p, r)
+input of the closing discussion, Sec. VII) obstacles are ``float32[Np][4]`` =
+(x, y, z, r) and the network has 10 inputs [p', r, a].
 
 All generators use numpy's PCG64 with an explicit seed.
 """
@@ -23,7 +26,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-IN_DIM = 9
+IN_DIM = 9          # point obstacles: network input [p', a]
+IN_DIM_SPHERE = 10  # sphere obstacles: network input [p', r, a]
 BLOB_MAGIC = b"GCDF"
 BLOB_VERSION = 1
 BLOB_HEADER_BYTES = 32  # magic, version, in_dim, width, depth, 3 reserved u32
@@ -122,11 +126,12 @@ class Weights:
     """Distance-MLP parameters, float32, out x in row-major (Sec. III-C network)."""
     width: int
     depth: int
-    mats: list  # [W1 (W x 9), W2..W_depth (W x W), w_out (1 x W)]
+    mats: list  # [W1 (W x in_dim), W2..W_depth (W x W), w_out (1 x W)]
     biases: list  # [b1 (W), ..., b_depth (W), b_out (1)]
+    in_dim: int = IN_DIM
 
     def to_blob(self) -> bytes:
-        hdr = BLOB_MAGIC + struct.pack("<7I", BLOB_VERSION, IN_DIM, self.width, self.depth, 0, 0, 0)
+        hdr = BLOB_MAGIC + struct.pack("<7I", BLOB_VERSION, self.in_dim, self.width, self.depth, 0, 0, 0)
         assert len(hdr) == BLOB_HEADER_BYTES
         parts = [hdr]
         for m, b in zip(self.mats, self.biases):
@@ -139,11 +144,11 @@ class Weights:
         if blob[:4] != BLOB_MAGIC:
             raise ValueError("bad weight blob magic")
         version, in_dim, width, depth = struct.unpack("<4I", blob[4:20])
-        if version != BLOB_VERSION or in_dim != IN_DIM:
+        if version != BLOB_VERSION or in_dim not in (IN_DIM, IN_DIM_SPHERE):
             raise ValueError("unsupported weight blob")
         off = BLOB_HEADER_BYTES
         mats, biases = [], []
-        dims = [IN_DIM] + [width] * depth + [1]
+        dims = [in_dim] + [width] * depth + [1]
         for li in range(depth + 1):
             fi, fo = dims[li], dims[li + 1]
             m = np.frombuffer(blob, dtype="<f4", count=fo * fi, offset=off).reshape(fo, fi).copy()
@@ -154,7 +159,7 @@ class Weights:
             biases.append(b)
         if off != len(blob):
             raise ValueError("weight blob size mismatch")
-        return Weights(width, depth, mats, biases)
+        return Weights(width, depth, mats, biases, in_dim)
 
     def flat_params(self) -> list:
         out = []
@@ -163,15 +168,18 @@ class Weights:
         return out
 
 
-def weights(width: int, seed: int, depth: int = 4, bf16_hidden: bool = True) -> Weights:
+def weights(width: int, seed: int, depth: int = 4, bf16_hidden: bool = True, in_dim: int = IN_DIM) -> Weights:
     """He-normal weights N(0, 2/fan_in) for every layer, biases U(+-1/sqrt(fan_in)).
 
     Draw order W1, b1, W2, b2, ..., w_out, b_out from one PCG64 stream.  The
     square hidden matrices W2..W_depth are rounded to the bfloat16 grid so that
-    a BF16 matrix-core path multiplies by exactly the same weights.
+    a BF16 matrix-core path multiplies by exactly the same weights.  in_dim 10
+    gives the sphere-obstacle network (W1 columns p'x, p'y, p'z, r, a1..a6).
     """
+    if in_dim not in (IN_DIM, IN_DIM_SPHERE):
+        raise ValueError("in_dim must be 9 or 10")
     r = _rng(seed)
-    dims = [IN_DIM] + [width] * depth + [1]
+    dims = [in_dim] + [width] * depth + [1]
     mats, biases = [], []
     for li in range(depth + 1):
         fi, fo = dims[li], dims[li + 1]
@@ -182,7 +190,16 @@ def weights(width: int, seed: int, depth: int = 4, bf16_hidden: bool = True) -> 
             m = round_to_bf16_grid(m)
         mats.append(m)
         biases.append(b)
-    return Weights(width, depth, mats, biases)
+    return Weights(width, depth, mats, biases, in_dim)
+
+
+def spheres(Np: int, seed: int, r_lo: float = 0.05, r_hi: float = 0.25) -> np.ndarray:
+    """Np sphere obstacles ``float32[Np][4]`` = (x, y, z, r): centres from the
+    patch cloud of the same seed (points_patches), radii U[r_lo, r_hi] m from a
+    second PCG64 stream (seed + 7919)."""
+    c = points_patches(Np, seed)
+    rad = _rng(seed + 7919).uniform(r_lo, r_hi, size=(Np, 1))
+    return np.ascontiguousarray(np.concatenate([c, rad.astype(np.float32)], axis=1), dtype=np.float32)
 
 
 # ----------------------------------------------------------------------------
