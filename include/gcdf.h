@@ -22,9 +22,18 @@
  *   d[i*Np + j]          distance for knot i, point j
  *   J[(i*Np + j)*9 + c]  d d / d q_i[c], c in (x, y, yaw, a1..a6)
  *
+ * Sphere obstacles (the primitive-aware GCDF over (q, p, r) of the closing
+ * discussion, Sec. VII): a context created from a blob with in_dim = 10 takes
+ * obstacles as spheres float32[Np][4] = (x, y, z, r) and evaluates the
+ * network on [p', r, a1..a6]; the radius is not moved by the base-frame
+ * transform, and J is still the gradient over the 9 configuration
+ * coordinates.  Every query, partition and serving call below then reads
+ * 4 floats per obstacle where it says "points".
+ *
  * Memory: every knots/points/output pointer is DEVICE memory owned by the
  * caller (e.g. a torch tensor).  knots is float32[K][9] (x, y, yaw, a1..a6),
- * points is float32[Np][3] world coordinates.  The library never frees caller
+ * points is float32[Np][3] world coordinates (float32[Np][4] spheres for an
+ * in_dim 10 network).  The library never frees caller
  * memory.  Calls are asynchronous on the caller's HIP stream (hipStream_t
  * passed as void*; NULL = the null stream) and never synchronise the host;
  * the caller synchronises the stream before reading outputs.
@@ -78,13 +87,14 @@ typedef struct gcdf_ctx gcdf_ctx;
 
 /* Create a context from a weight blob (host memory, copied; the caller keeps
  * ownership).  Blob format, little-endian: "GCDF", u32 version = 1,
- * u32 in_dim = 9, u32 width, u32 depth, 3 reserved u32, then float32 arrays
- * W1 (width x 9), b1, W2 (width x width), b2, ..., W_depth, b_depth,
+ * u32 in_dim = 9 (points, input [p', a]) or 10 (spheres, input [p', r, a]),
+ * u32 width, u32 depth, 3 reserved u32, then float32 arrays
+ * W1 (width x in_dim), b1, W2 (width x width), b2, ..., W_depth, b_depth,
  * w_out (1 x width), b_out, each matrix row-major (out x in) -- the network of
  * Sec. III-C.  For the BF16 precisions W2..W_depth are rounded to BF16
  * (round-to-nearest-even); blobs whose hidden matrices already lie on the BF16
  * grid are multiplied exactly.  Errors: EINVAL (bad config or blob: width not
- * 256/512, depth != 4, size mismatch), ENOMEM, EDEVICE. */
+ * 256/512, depth != 4, in_dim not 9 or 10, size mismatch), ENOMEM, EDEVICE. */
 gcdf_status gcdf_create(const gcdf_config* cfg, const void* weight_blob, size_t blob_bytes, gcdf_ctx** out);
 
 /* Destroy a context: waits for in-flight serving requests, then frees every
@@ -142,6 +152,9 @@ gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float
  * point j (points float32[Np][3]) is in partition i when
  * dx*dx + dy*dy <= radius*radius, evaluated in float32 with every product and
  * the sum rounded (no fused multiply-add), dx = px - x_i, dy = py - y_i.
+ * For a sphere context (points float32[Np][4], (x, y, z, s)) the sphere is in
+ * partition i when it reaches into the disc: radius*radius is replaced by
+ * t*t with t = radius + s, rounded the same way.
  * Writes offsets int64[N+1].  The caller reads offsets[N] (the total) to size
  * idx.  EINVAL: NULL pointers, N <= 0, Np <= 0 or > 2^31 - 1, ref_stride < 2,
  * radius negative or not finite. */
@@ -237,7 +250,8 @@ gcdf_status gcdf_poll(gcdf_ctx* ctx, uint64_t ticket);
 
 /* Sample i of a batch is the pair (knots[i], points[i]): one knot and one
  * point per sample, the network evaluated on [R(yaw)^T (p - t), a] as in the
- * query (the network of Sec. III-C, trained on (point, configuration) pairs). */
+ * query (the network of Sec. III-C, trained on (point, configuration) pairs).
+ * Training covers the point network (in_dim 9) only. */
 typedef struct gcdf_trainer gcdf_trainer;
 
 /* Number of float32 parameters of a width-W, depth-4 network: the weight-blob

@@ -153,6 +153,10 @@ class Context:
         _check(lib.gcdf_create(ctypes.byref(cfg), buf, len(weight_blob), ctypes.byref(h)))
         self._h = h
         self.width, self.precision, self.device = width, cfg.precision, device
+        # network input width from the blob header: 9 (points, (Np, 3)) or 10
+        # (spheres (x, y, z, r), (Np, 4)); the library has validated it
+        self.in_dim = int.from_bytes(weight_blob[8:12], "little")
+        self.obstacle_dim = self.in_dim - 6
 
     def close(self):
         if getattr(self, "_h", None):
@@ -177,7 +181,7 @@ class Context:
 
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         if d is None:
             d = torch.empty((K, Np), dtype=torch.float32, device=knots.device)
         _need(d, (K, Np), "d")
@@ -189,7 +193,7 @@ class Context:
 
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         if d is None:
             d = torch.empty((K, Np), dtype=torch.float32, device=knots.device)
         if J is None:
@@ -205,7 +209,7 @@ class Context:
 
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         dmin = torch.empty(K, dtype=torch.float32, device=knots.device)
         am = torch.empty(K, dtype=torch.int32, device=knots.device)
         Jm = torch.empty((K, 9), dtype=torch.float32, device=knots.device) if with_jacobian else None
@@ -217,7 +221,7 @@ class Context:
         """All requested outputs from one fused pass (preallocated tensors or None)."""
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         if d is not None:
             _need(d, (K, Np), "d")
         if J is not None:
@@ -236,7 +240,7 @@ class Context:
         if ref.dtype != torch.float32 or not ref.is_cuda or not ref.is_contiguous() or ref.dim() != 2:
             raise ValueError("ref must be a contiguous 2-D float32 CUDA tensor")
         N, Np = ref.shape[0], points.shape[0]
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         stride = ref.shape[1] if ref_stride is None else ref_stride
         off = torch.empty(N + 1, dtype=torch.int64, device=ref.device)
         lib = library()
@@ -254,7 +258,7 @@ class Context:
 
         N, Np, total = knots.shape[0], points.shape[0], idx.shape[0]
         _need(knots, (N, 9), "knots")
-        _need(points, (Np, 3), "points")
+        _need(points, (Np, self.obstacle_dim), "points")
         if offsets.dtype != torch.int64 or idx.dtype != torch.int32 or offsets.shape[0] != N + 1:
             raise ValueError("offsets must be int64[N+1] and idx int32[total]")
         if c is None:
@@ -305,6 +309,8 @@ class Context:
 
     # -- serving ------------------------------------------------------------
     def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None) -> int:
+        if points.dim() != 2 or points.shape[1] != self.obstacle_dim:
+            raise ValueError("points must be (Np, %d)" % self.obstacle_dim)
         req = _Request()
         req.knots, req.K = knots.data_ptr(), knots.shape[0]
         req.points, req.Np = points.data_ptr(), points.shape[0]

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgcdf.so")
-SOURCES = ["gcdf_fused.hip", "gcdf_constraints.hip", "gcdf_optim.hip", "gcdf_api.cpp", "gcdf_serve.cpp", "gcdf_train.cpp"]
+SOURCES = ["gcdf_fused.hip", "gcdf_sphere.hip", "gcdf_serve_kernel.hip", "gcdf_constraints.hip", "gcdf_optim.hip", "gcdf_api.cpp", "gcdf_serve.cpp", "gcdf_train.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -99,12 +99,16 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
     return fail(GCDF_EINVAL, "unknown precision %d", cfg->precision);
   if (cfg->max_knots < 0) return fail(GCDF_EINVAL, "max_knots must be >= 0");
   const int W = cfg->width;
-  // blob: header + W1, b1, (W2, b2) .. (W4, b4), w_out, b_out
-  const size_t nfloat = (size_t)W * 9 + W + 3 * ((size_t)W * W + W) + W + 1;
-  if (bytes != kHeader + 4 * nfloat) return fail(GCDF_EINVAL, "weight blob is %zu bytes, expected %zu", bytes, kHeader + 4 * nfloat);
+  if (bytes < kHeader) return fail(GCDF_EINVAL, "weight blob is %zu bytes, shorter than its header", bytes);
   const uint32_t* hdr = static_cast<const uint32_t*>(blob);
-  if (std::memcmp(blob, "GCDF", 4) != 0 || hdr[1] != 1 || hdr[2] != 9 || (int)hdr[3] != W || (int)hdr[4] != 4)
+  // in_dim 9: point obstacles, input [p', a]; 10: sphere obstacles, input [p', r, a]
+  const int in_dim = (int)hdr[2];
+  if (std::memcmp(blob, "GCDF", 4) != 0 || hdr[1] != 1 || (in_dim != gcdf::kInDim && in_dim != gcdf::kInDimSphere) ||
+      (int)hdr[3] != W || (int)hdr[4] != 4)
     return fail(GCDF_EINVAL, "weight blob header does not match (magic/version/in_dim/width/depth)");
+  // blob: header + W1, b1, (W2, b2) .. (W4, b4), w_out, b_out
+  const size_t nfloat = (size_t)W * in_dim + W + 3 * ((size_t)W * W + W) + W + 1;
+  if (bytes != kHeader + 4 * nfloat) return fail(GCDF_EINVAL, "weight blob is %zu bytes, expected %zu", bytes, kHeader + 4 * nfloat);
 
   int dev = cfg->device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(GCDF_EDEVICE, "no current HIP device");
@@ -148,7 +152,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   char* base = static_cast<char*>(c->wbuf);
   // offsets of the source arrays inside staging (floats)
   const float* W1 = staging;
-  const float* b1 = W1 + (size_t)W * 9;
+  const float* b1 = W1 + (size_t)W * in_dim;
   const float* Wl[3];
   const float* bl[3];
   {
@@ -164,7 +168,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   float* bh = reinterpret_cast<float*>(base + off_bh);
   float* w5 = reinterpret_cast<float*>(base + off_w5);
   // biases b2..b4 are not contiguous in the blob: reorder them one by one
-  if (e == hipSuccess) e = gcdf::pack_input_layer(W1, b1, w1p, W, s);
+  if (e == hipSuccess) e = gcdf::pack_input_layer(W1, b1, w1p, W, in_dim, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l) e = gcdf::pack_row_vectors(bl[l], bh + (size_t)l * W, W, 1, s);
   if (e == hipSuccess) e = gcdf::pack_row_vectors(w5src, w5, W, 1, s);
   if (e == hipSuccess) e = hipMemcpyAsync(base + off_b5, staging + nfloat - 1, 4, hipMemcpyDeviceToDevice, s);
@@ -185,6 +189,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   }
   c->net.width = W;
   c->net.mode = mode;
+  c->net.in_dim = in_dim;
   c->net.w1p = w1p;
   c->net.bh = bh;
   c->net.w5 = w5;
@@ -280,8 +285,8 @@ gcdf_status gcdf_partition_count(gcdf_ctx* ctx, const float* ref, int64_t N, int
   if (ref_stride < 2) return fail(GCDF_EINVAL, "ref_stride must be >= 2 (got %lld)", (long long)ref_stride);
   if (!(radius >= 0.f) || radius > 3.0e38f) return fail(GCDF_EINVAL, "radius must be finite and >= 0");
   DeviceGuard guard(ctx->device);
-  hipError_t e = gcdf::launch_partition_count(ref, N, ref_stride, points, Np, radius, offsets,
-                                              static_cast<hipStream_t>(stream));
+  hipError_t e = gcdf::launch_partition_count(ref, N, ref_stride, points, Np, ctx->net.in_dim == gcdf::kInDimSphere,
+                                              radius, offsets, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_partition_count launch");
 }
 
@@ -297,8 +302,8 @@ gcdf_status gcdf_partition_fill(gcdf_ctx* ctx, const float* ref, int64_t N, int6
   if (capacity < 0 || (capacity > 0 && !idx)) return fail(GCDF_EINVAL, "idx is NULL or capacity < 0");
   if (capacity == 0) return GCDF_OK;
   DeviceGuard guard(ctx->device);
-  hipError_t e = gcdf::launch_partition_fill(ref, N, ref_stride, points, Np, radius, offsets, idx, capacity,
-                                             static_cast<hipStream_t>(stream));
+  hipError_t e = gcdf::launch_partition_fill(ref, N, ref_stride, points, Np, ctx->net.in_dim == gcdf::kInDimSphere,
+                                             radius, offsets, idx, capacity, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_partition_fill launch");
 }
 

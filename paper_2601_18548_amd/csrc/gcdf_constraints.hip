@@ -8,7 +8,9 @@
 // Membership: point j is in partition i when its planar distance to reference
 // base position i is within the radius, decided in float32 as
 // rn(rn(dx*dx) + rn(dy*dy)) <= rn(r*r) with no fused multiply-add, so the count
-// and fill passes (and any reimplementation) take the same decision.
+// and fill passes (and any reimplementation) take the same decision.  Sphere
+// obstacles (x, y, z, s) of the primitive-aware network are in range when they
+// reach into the disc: the same test with r replaced by rn(r + s).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,16 +24,21 @@ constexpr int kPartThreads = 256;
 constexpr int kPartPerThread = 16;  // count pass: points per thread per workgroup
 constexpr int kFillPerThread = 4;   // fill pass: points per thread per round
 
-__device__ __forceinline__ bool in_range(const float* __restrict__ points, int64_t j, float rx, float ry, float r2) {
-#pragma clang fp contract(off)
-  const float dx = points[3 * j] - rx;
-  const float dy = points[3 * j + 1] - ry;
-  return dx * dx + dy * dy <= r2;
-}
-
 __device__ __forceinline__ float squared(float r) {
 #pragma clang fp contract(off)
   return r * r;
+}
+
+// r2 = rn(radius * radius), used as is for points
+template <bool SPH>
+__device__ __forceinline__ bool in_range(const float* __restrict__ points, int64_t j, float rx, float ry, float radius,
+                                         float r2) {
+#pragma clang fp contract(off)
+  const float* p = points + (SPH ? 4 : 3) * j;
+  const float dx = p[0] - rx;
+  const float dy = p[1] - ry;
+  const float lim = SPH ? squared(radius + p[3]) : r2;
+  return dx * dx + dy * dy <= lim;
 }
 
 __global__ void zero_i64_kernel(int64_t* __restrict__ p, int64_t n) {
@@ -40,6 +47,7 @@ __global__ void zero_i64_kernel(int64_t* __restrict__ p, int64_t n) {
 }
 
 // grid (chunks of kPartThreads * kPartPerThread points, N): counts[i] += members in the chunk.
+template <bool SPH>
 __global__ __launch_bounds__(kPartThreads) void partition_count_kernel(const float* __restrict__ ref, int64_t ref_stride,
                                                                        const float* __restrict__ points, int64_t M,
                                                                        float radius, int64_t* __restrict__ counts) {
@@ -51,7 +59,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_count_kernel(const flo
 #pragma unroll 4
   for (int u = 0; u < kPartPerThread; ++u) {
     const int64_t j = j0 + (int64_t)u * kPartThreads;
-    if (j < M && in_range(points, j, rx, ry, r2)) ++c;
+    if (j < M && in_range<SPH>(points, j, rx, ry, radius, r2)) ++c;
   }
   for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
@@ -95,6 +103,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_scan_kernel(int64_t* _
 // One workgroup per partition, rounds of kPartThreads * kFillPerThread points in
 // ascending order; inside a round point j = j0 + u * 256 + wave * 64 + lane, ranked
 // by (u, wave, lane) with ballots, so the indices come out ascending.
+template <bool SPH>
 __global__ __launch_bounds__(kPartThreads) void partition_fill_kernel(const float* __restrict__ ref, int64_t ref_stride,
                                                                       const float* __restrict__ points, int64_t M,
                                                                       float radius, const int64_t* __restrict__ offsets,
@@ -114,7 +123,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_fill_kernel(const floa
 #pragma unroll
     for (int u = 0; u < kFillPerThread; ++u) {
       const int64_t j = j0 + u * kPartThreads + threadIdx.x;
-      in[u] = j < M && in_range(points, j, rx, ry, r2);
+      in[u] = j < M && in_range<SPH>(points, j, rx, ry, radius, r2);
       const uint64_t m = __ballot(in[u]);
       rank[u] = __popcll(m & below);
       if (lane == 0) wcnt[buf][u][wave] = __popcll(m);
@@ -263,7 +272,7 @@ hipError_t launch_project(const float* knots, int64_t N, int64_t Np, const int64
 }
 
 hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
-                                  float radius, int64_t* offsets, hipStream_t s) {
+                                  bool spheres, float radius, int64_t* offsets, hipStream_t s) {
   hipLaunchKernelGGL(zero_i64_kernel, dim3((unsigned)((N + 1 + 255) / 256)), dim3(256), 0, s, offsets, N + 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -271,8 +280,12 @@ hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_strid
   const int64_t chunks = (M + per - 1) / per;
   for (int64_t n0 = 0; n0 < N; n0 += 65535) {  // grid.y limit
     const int64_t n = N - n0 < 65535 ? N - n0 : 65535;
-    hipLaunchKernelGGL(partition_count_kernel, dim3((unsigned)chunks, (unsigned)n), dim3(kPartThreads), 0, s,
-                       ref + n0 * ref_stride, ref_stride, points, M, radius, offsets + 1 + n0);
+    if (spheres)
+      hipLaunchKernelGGL(partition_count_kernel<true>, dim3((unsigned)chunks, (unsigned)n), dim3(kPartThreads), 0, s,
+                         ref + n0 * ref_stride, ref_stride, points, M, radius, offsets + 1 + n0);
+    else
+      hipLaunchKernelGGL(partition_count_kernel<false>, dim3((unsigned)chunks, (unsigned)n), dim3(kPartThreads), 0, s,
+                         ref + n0 * ref_stride, ref_stride, points, M, radius, offsets + 1 + n0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -281,10 +294,14 @@ hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_strid
 }
 
 hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
-                                 float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
+                                 bool spheres, float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(partition_fill_kernel, dim3((unsigned)N), dim3(kPartThreads), 0, s, ref, ref_stride, points, M,
-                     radius, offsets, idx, capacity);
+  if (spheres)
+    hipLaunchKernelGGL(partition_fill_kernel<true>, dim3((unsigned)N), dim3(kPartThreads), 0, s, ref, ref_stride,
+                       points, M, radius, offsets, idx, capacity);
+  else
+    hipLaunchKernelGGL(partition_fill_kernel<false>, dim3((unsigned)N), dim3(kPartThreads), 0, s, ref, ref_stride,
+                       points, M, radius, offsets, idx, capacity);
   return hipGetLastError();
 }
 

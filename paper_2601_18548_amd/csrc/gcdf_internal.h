@@ -5,7 +5,8 @@
 
 namespace gcdf {
 
-constexpr int kInDim = 9;
+constexpr int kInDim = 9;         // configuration coordinates per knot (x, y, yaw, a1..a6)
+constexpr int kInDimSphere = 10;  // network inputs for sphere obstacles: [p', r, a]
 constexpr int kTileQ = 64;   // queries per tile (two 32-wide MFMA column blocks)
 constexpr int kWaves = 4;    // waves per workgroup, one per SIMD
 constexpr int kThreads = 64 * kWaves;
@@ -18,7 +19,8 @@ enum Mode : int { kFP32 = 0, kBF16 = 1, kBF16X2 = 2 };
 struct DevNet {
   int width;
   int mode;
-  const float* w1p;   // [width][12]: W1[r][0..2], b1[r], W1[r][3..8], 0, 0
+  int in_dim;         // 9: point obstacles [Np][3]; 10: spheres [Np][4], input [p', r, a]
+  const float* w1p;   // [width][12]: W1[r][p'x, p'y, p'z], b1[r], W1[r][a1..a6], W1[r][radius] (0 when in_dim 9), 0
   const float* bh;    // [depth-1][width]: b2, b3, b4
   const float* w5;    // [width]
   const float* b5p;   // device pointer to the output bias
@@ -73,20 +75,21 @@ size_t packed_matrix_bytes(int width, int mode);
 // A-fragment layout (device), transposing first if `transpose`.
 hipError_t pack_matrix(const float* src, void* dst, int width, int mode, bool transpose, hipStream_t s);
 
-// Build w1p (device) from W1 [width][9] and b1 [width] (device).
-hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int width, hipStream_t s);
+// Build w1p (device) from W1 [width][in_dim] and b1 [width] (device).
+hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int width, int in_dim, hipStream_t s);
 
 // Reorder nvec consecutive row vectors of length width into lane-major row order.
 hipError_t pack_row_vectors(const float* src, float* dst, int width, int nvec, hipStream_t s);
 
 // Obstacle partitions: offsets[i+1] - offsets[i] = number of points within `radius`
 // (planar distance) of reference base position i (ref + i * ref_stride), offsets[0] = 0.
+// spheres: points hold (x, y, z, s) and the limit is radius + s.
 hipError_t launch_partition_count(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
-                                  float radius, int64_t* offsets, hipStream_t s);
+                                  bool spheres, float radius, int64_t* offsets, hipStream_t s);
 // idx[offsets[i] + k] = k-th point (ascending) of partition i; entries at positions >=
 // capacity are not written.
 hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride, const float* points, int64_t M,
-                                 float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
+                                 bool spheres, float radius, const int64_t* offsets, int32_t* idx, int64_t capacity,
                                  hipStream_t s);
 // tile_off[0] = 0, tile_off[i+1] = tile_off[i] + ceil((offsets[i+1] - offsets[i]) / 64).
 hipError_t launch_csr_tile_offsets(const int64_t* offsets, int64_t N, int64_t* tile_off, hipStream_t s);
@@ -107,6 +110,9 @@ hipError_t launch_project(const float* knots, int64_t N, int64_t Np, const int64
 
 // Launch the fused query kernel (dense all-pairs if !pairs, else the pair list).
 hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu, hipStream_t s);
+// The same for a sphere network (net.in_dim == 10; points hold (x, y, z, r)); no training.
+hipError_t launch_fused_sphere(const DevNet& net, const Job& job, bool pairs, bool want_grad, int num_cu,
+                               hipStream_t s);
 
 // minkey[i] = all ones, for i < K (fill kernel; graph-capture safe).
 hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t s);

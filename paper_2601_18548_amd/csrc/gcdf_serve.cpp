@@ -80,9 +80,9 @@ struct Ticket {
   int64_t key_off = -1;
 };
 
-size_t request_bytes(const gcdf_request& r) {
+size_t request_bytes(const gcdf_request& r, int obstacle_floats) {
   const size_t pairs = (size_t)r.K * (size_t)r.Np;
-  size_t b = (size_t)r.K * 36 + (size_t)r.Np * 12;
+  size_t b = (size_t)r.K * 36 + (size_t)r.Np * 4 * obstacle_floats;
   if (r.d) b += pairs * 4;
   if (r.J) b += pairs * 36;
   if (r.dmin) b += (size_t)r.K * 16;  // dmin + argmin + key scratch
@@ -287,7 +287,7 @@ gcdf_status server_submit(Server* sv, const gcdf_request* r, uint64_t* ticket) {
   if ((r->dmin == nullptr) != (r->argmin == nullptr)) return set_error(GCDF_EINVAL, "dmin and argmin go together");
   if (r->dmin && r->Np > INT32_MAX) return set_error(GCDF_EINVAL, "request Np exceeds 2^31-1");
   if (r->K * ((r->Np + kTileQ - 1) / kTileQ) >= ((int64_t)1 << 32)) return set_error(GCDF_EINVAL, "request too large");
-  const size_t bytes = request_bytes(*r);
+  const size_t bytes = request_bytes(*r, ctx_net(sv->ctx).in_dim == kInDimSphere ? 4 : 3);
   if (bytes > sv->budget) return set_error(GCDF_ENOMEM, "request needs more memory than serve_mem_budget");
   if (r->dmin && r->K > sv->key_cap) return set_error(GCDF_ENOMEM, "request K exceeds the key scratch");
   std::lock_guard<std::mutex> lk(sv->mu);

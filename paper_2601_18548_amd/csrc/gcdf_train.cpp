@@ -74,7 +74,8 @@ struct DevGuard {
 hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
   const Offsets o(tr->W);
   char* base = static_cast<char*>(tr->wbuf);
-  hipError_t e = gcdf::pack_input_layer(params + o.W1, params + o.b1, const_cast<float*>(tr->net.w1p), tr->W, s);
+  hipError_t e = gcdf::pack_input_layer(params + o.W1, params + o.b1, const_cast<float*>(tr->net.w1p), tr->W,
+                                        gcdf::kInDim, s);
   for (int l = 0; l < 3 && e == hipSuccess; ++l)
     e = gcdf::pack_row_vectors(params + o.bl[l], const_cast<float*>(tr->net.bh) + (size_t)l * tr->W, tr->W, 1, s);
   if (e == hipSuccess) e = gcdf::pack_row_vectors(params + o.w5, const_cast<float*>(tr->net.w5), tr->W, 1, s);
@@ -140,6 +141,7 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   char* base = static_cast<char*>(tr->wbuf);
   tr->net.width = W;
   tr->net.mode = precision;
+  tr->net.in_dim = gcdf::kInDim;  // training takes point networks
   tr->net.w1p = reinterpret_cast<float*>(base + off_w1);
   tr->net.bh = reinterpret_cast<float*>(base + off_bh);
   tr->net.w5 = reinterpret_cast<float*>(base + off_w5);

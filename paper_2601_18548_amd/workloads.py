@@ -223,6 +223,8 @@ def workload(name: str, seed: int = 0) -> QueryWorkload:
     small   : 16 knots x 64 uniform points, width 256 (1,024 pairs)
     fp32    : 64 knots x 4,096 patch points, width 256, FP32 (262,144 pairs)
     bf16    : 128 knots x 16,384 patch points, width 512, BF16 (2,097,152 pairs)
+    sphere  : the bf16 shape with sphere obstacles (patch-cloud centres, radii
+              U[0.05, 0.25] m) and the 10-input network [p', r, a]
     """
     if name == "small":
         return QueryWorkload(name, 16, 64, 256, "fp32", knots(16, seed + 1),
@@ -233,6 +235,9 @@ def workload(name: str, seed: int = 0) -> QueryWorkload:
     if name == "bf16":
         return QueryWorkload(name, 128, 16384, 512, "bf16x2", knots(128, seed + 1),
                              points_patches(16384, seed + 2), weights(512, seed + 3))
+    if name == "sphere":
+        return QueryWorkload(name, 128, 16384, 512, "bf16x2", knots(128, seed + 1),
+                             spheres(16384, seed + 2), weights(512, seed + 3, in_dim=IN_DIM_SPHERE))
     raise KeyError(name)
 
 
