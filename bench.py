@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16x2": 2500.0, "bf16": 2500.0, "fp32": 157.3}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_query_bf16_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2601_18548_amd", "csrc", "gcdf_fused.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_18548_amd", "csrc", "gcdf_tile.h")  # the query kernel's code
 
 
 def flops_per_pair(width: int) -> int:
@@ -215,6 +215,32 @@ def constraints_bench(g, torch, wk, reps: int = 5, n_knots: int = 128, radius: f
     return out
 
 
+def sphere_bench(g, torch, point_kernel_ms: float, reps: int = 10):
+    """Sphere obstacles (x, y, z, r) with the 10-input network [p', r, a]: the
+    benchmark shape (128 knots x 16,384 spheres, width 512, BF16X2), one fused
+    eval_grad launch per rep, timed with HIP events on its stream."""
+    from paper_2601_18548_amd import workloads as wl
+
+    wk = wl.workload("sphere")
+    ctx = g.Context(wk.weights.to_blob(), wk.width, wk.precision)
+    stream = torch.cuda.current_stream()
+    kt = torch.from_numpy(wk.knots).cuda()
+    st = torch.from_numpy(wk.points).cuda()
+    d = torch.empty((wk.K, wk.Np), device="cuda")
+    J = torch.empty((wk.K, wk.Np, 9), device="cuda")
+    ctx.eval_grad(kt, st, d, J)
+    ms = _event_ms(torch, stream, lambda: ctx.eval_grad(kt, st, d, J, stream=stream), reps)
+    pairs = wk.K * wk.Np
+    # input layer 20 W (one more input than points), its gradient 18 W (the nine
+    # configuration-facing inputs), output 2 W
+    fl = (12 * wk.width * wk.width + 40 * wk.width) * pairs
+    tf = fl / (ms * 1e-3) / 1e12
+    ctx.close()
+    return {"workload": "128 knots x 16384 spheres (x, y, z, r), width 512, bf16x2, input [p', r, a]",
+            "kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS["bf16x2"],
+            "vs_point_kernel": point_kernel_ms / ms}
+
+
 def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
     """Training step of the width-256 network: MSE against a seeded teacher's
     distances plus N(0, 1e-3) noise, hand-written forward/backward behind
@@ -332,6 +358,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--no-constraints", action="store_true", help="skip the partition / CSR / projection leg")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the sphere-obstacle leg")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     args = ap.parse_args()
@@ -426,6 +453,9 @@ def main():
     if not args.no_constraints and args.workload == "bf16":
         out["constraints"] = constraints_bench(g, torch, wk)
         print("bench: constraints %s" % json.dumps(out["constraints"]), file=sys.stderr, flush=True)
+    if not args.no_sphere and args.workload == "bf16":
+        out["sphere"] = sphere_bench(g, torch, kernel_ms)
+        print("bench: sphere %s" % json.dumps(out["sphere"]), file=sys.stderr, flush=True)
     if args.train_steps > 0:
         out["training"] = train_bench(torch, args.train_steps, 3)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
