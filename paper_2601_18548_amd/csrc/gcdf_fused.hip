@@ -27,9 +27,9 @@ __device__ __forceinline__ void silu_d12(float z, float& d1, float& d2) {
 }
 
 template <int W>
-__global__ __launch_bounds__(kThreads, 1) void table1_tiles(const DevNet net, const T1Job job, int64_t ntiles) {
+__global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(const DevNet net, const T1Job job, int64_t ntiles) {
   constexpr int MODE = kFP32;
-  using G = Geo<W>;
+  using G = Geo<W, MODE>;
   constexpr int MT = G::MT;
   constexpr int XF = G::XIN_FLOATS;
   __shared__ __attribute__((aligned(16))) char lds[G::LDS_BYTES];
@@ -38,7 +38,9 @@ __global__ __launch_bounds__(kThreads, 1) void table1_tiles(const DevNet net, co
   const Bases<W, MODE>& b = tc.b;
   float* uin = tc.red;  // [64][9] tangent direction of the tile's samples
   const int tid = threadIdx.x;
-  const size_t arr = (size_t)kThreads * 64;
+  constexpr int NTH = G::THREADS;
+  static_assert(NTH == kThreads, "gcdf_train_table1 sizes the scratch for kThreads threads per workgroup");
+  const size_t arr = (size_t)NTH * 64;
   float* scr = job.scratch + (size_t)blockIdx.x * kT1ScratchArrays * arr;
   float* sZ = scr;             // z_1..z_4
   float* sZd = scr + 4 * arr;  // zdot_1..zdot_4
@@ -47,10 +49,10 @@ __global__ __launch_bounds__(kThreads, 1) void table1_tiles(const DevNet net, co
   // float4 idx of this thread in a scratch array (elements 4 (idx % 4) .. +3 of
   // accumulator (i, nt) with idx / 4 = i * 2 + nt)
   auto sget = [&](const float* base, int idx) {
-    return *reinterpret_cast<const f32x4*>(base + ((size_t)idx * kThreads + tid) * 4);
+    return *reinterpret_cast<const f32x4*>(base + ((size_t)idx * NTH + tid) * 4);
   };
   auto sput = [&](float* base, int idx, const f32x4& v) {
-    *reinterpret_cast<f32x4*>(base + ((size_t)idx * kThreads + tid) * 4) = v;
+    *reinterpret_cast<f32x4*>(base + ((size_t)idx * NTH + tid) * 4) = v;
   };
   auto zero = [&](f32x16 (&x)[MT][2]) {
 #pragma unroll
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(kThreads, 1) void table1_tiles(const DevNet net, co
 hipError_t launch_table1_tiles(const DevNet& net, const T1Job& job, int grid, hipStream_t s) {
   if (net.width != 256 || net.mode != kFP32) return hipErrorInvalidValue;
   const int64_t ntiles = (job.B + kTileQ - 1) / kTileQ;
-  hipLaunchKernelGGL(table1_tiles<256>, dim3((unsigned)grid), dim3(kThreads), 0, s, net, job, ntiles);
+  hipLaunchKernelGGL(table1_tiles<256>, dim3((unsigned)grid), dim3((Geo<256, kFP32>::THREADS)), 0, s, net, job, ntiles);
   return hipGetLastError();
 }
 

@@ -28,9 +28,9 @@ __device__ __forceinline__ T sys_relaxed(const T* p) {
 }
 
 template <int W, int MODE, bool SPH>
-__global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, ServeCtl* ctl, ServeDev* dev,
+__global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const DevNet net, ServeCtl* ctl, ServeDev* dev,
                                                           uint64_t first_seq, uint64_t idle_ticks, uint32_t epoch) {
-  __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES];
   __shared__ int64_t claim_info[3];  // claimed seq (or -1: exit, -2: none), tile, seq to finalize (or -1)
   __shared__ ServeDesc cur;          // the request this workgroup is working on
   __shared__ ServeDesc fin;          // a request this workgroup completes
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
     if (claim_info[2] >= 0) {
       // this workgroup completed request fin.seq: per-knot minimum, key scratch restored
       if (fin.dmin) {
-        for (int64_t k = tid; k < fin.K; k += kThreads) {
+        for (int64_t k = tid; k < fin.K; k += Geo<W, MODE>::THREADS) {
           const unsigned long long key = __hip_atomic_load(fin.minkey + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const uint32_t o = (uint32_t)(key >> 32);
           const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kThreads, 1) void serve_loop(const DevNet net, Serv
 template <int W, int MODE, bool SPH>
 static hipError_t launch_serve_t(const DevNet& net, ServeCtl* ctl, ServeDev* dev, uint64_t first_seq,
                                  uint64_t idle_ticks, uint32_t epoch, int num_cu, hipStream_t s) {
-  hipLaunchKernelGGL((serve_loop<W, MODE, SPH>), dim3(num_cu), dim3(kThreads), 0, s, net, ctl, dev, first_seq, idle_ticks,
+  hipLaunchKernelGGL((serve_loop<W, MODE, SPH>), dim3(num_cu), dim3((Geo<W, MODE>::THREADS)), 0, s, net, ctl, dev, first_seq, idle_ticks,
                      epoch);
   return hipGetLastError();
 }

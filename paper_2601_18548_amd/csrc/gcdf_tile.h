@@ -109,16 +109,37 @@ __device__ __forceinline__ float input_preact_t(float c, float w0, float w1, flo
   return input_preact(c, w0, w1, w2, x);
 }
 
-template <int W>
+// Waves per workgroup: 8 (two per SIMD) for width 512 on BF16 matrix cores, where
+// the per-wave registers of four waves (accumulators, parked SiLU' values, the
+// weight prefetch) would fill the register file and leave nothing to hide the
+// weight stream's L2 latency; 4 otherwise.
+template <int W, int MODE>
+constexpr int waves_for() {
+  return MODE != kFP32 ? 8 : 4;
+}
+
+template <int W, int MODE>
 struct Geo {
-  static constexpr int MT = W / (32 * kWaves);       // 32-row M tiles per wave
+  static constexpr int NW = waves_for<W, MODE>();    // waves per workgroup
+  static constexpr int THREADS = 64 * NW;
+  static constexpr int MT = W / (32 * NW);           // 32-row M tiles per wave
+  // The packed matrices and row vectors are laid out for 4 row groups of PMT M
+  // tiles each (pack_matrix, lane_major_pos); with 8 waves, waves 2p and 2p+1
+  // split row group p, SUB waves per group.
+  static constexpr int PMT = W / (32 * kWaves);
+  static constexpr int SUB = NW / kWaves;
+  // the per-query reduction buffer shares the activation tile when 8 waves would
+  // not leave room for it (the tile is idle by then)
+  static constexpr bool RED_IN_ACT = NW > kWaves;
   static constexpr int NKB = W / 16;                 // 16-deep K blocks (bf16)
   static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
   static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
   static constexpr int XIN_FLOATS = 17;              // per query: p'(3), cos, sin, arm(6), seed, radius, pad; odd stride: lanes reading one field of 32 queries hit 32 different banks
   static constexpr int RED_VALS = 10;                // d + 9 input-gradient components
-  static constexpr int LDS_BYTES =
-      ACT_BYTES + kTileQ * XIN_FLOATS * 4 + W * 4 + kWaves * RED_VALS * kTileQ * 4 + 4 * W * 4;
+  static constexpr int RED_BYTES = NW * RED_VALS * kTileQ * 4;
+  static constexpr int LDS_BYTES = ACT_BYTES + kTileQ * XIN_FLOATS * 4 + W * 4 + (RED_IN_ACT ? 0 : RED_BYTES) + 4 * W * 4;
+  static_assert(!RED_IN_ACT || RED_BYTES <= ACT_BYTES, "reduction buffer must fit the activation tile");
+  static_assert(MT >= 1 && PMT == SUB * MT, "row groups must split evenly");
 };
 
 // ----------------------------------------------------------------------------
@@ -138,7 +159,7 @@ struct Geo {
 // ----------------------------------------------------------------------------
 template <int W, int MODE>
 struct Lane {
-  static constexpr int MT = W / (32 * kWaves);
+  static constexpr int MT = Geo<W, MODE>::MT;
   int lane, wave, h, n0, kh, rbase;
   char* act_w;        // write base, hi plane (or the fp32 tile)
   char* act_w_lo;     // write base, lo plane
@@ -255,11 +276,11 @@ __device__ __forceinline__ void load_b(BFrag<MODE>& b, const char* br) {
   }
 }
 
-template <int W>
-__device__ __forceinline__ void load_a(f32x4 (&af)[Geo<W>::MT], __amdgpu_buffer_rsrc_t rs, int voff, int step) {
-  const int soff = step * Geo<W>::MT * 1024;
+template <int W, int MODE>
+__device__ __forceinline__ void load_a(f32x4 (&af)[(Geo<W, MODE>::MT)], __amdgpu_buffer_rsrc_t rs, int voff, int step) {
+  const int soff = step * Geo<W, MODE>::PMT * 1024;
 #pragma unroll
-  for (int i = 0; i < Geo<W>::MT; ++i)
+  for (int i = 0; i < Geo<W, MODE>::MT; ++i)
     af[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + i * 1024, soff, 0));
 }
 
@@ -269,11 +290,11 @@ __device__ __forceinline__ void load_a(f32x4 (&af)[Geo<W>::MT], __amdgpu_buffer_
 // are free as soon as its last MFMA has issued.  The scheduling barriers keep
 // the compiler from sinking the loads to the end of the loop body.
 template <int W, int MODE>
-__device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[Geo<W>::MT][2], f32x4 (&af)[Geo<W>::MT],
+__device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], f32x4 (&af)[(Geo<W, MODE>::MT)],
                                                 const BFrag<MODE>& b, __amdgpu_buffer_rsrc_t rs, int voff,
                                                 int next) {
-  constexpr int MT = Geo<W>::MT;
-  const int soff = next * MT * 1024;
+  constexpr int MT = Geo<W, MODE>::MT;
+  const int soff = next * Geo<W, MODE>::PMT * 1024;
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
     if constexpr (MODE == kFP32) {
@@ -304,14 +325,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* base) 
 }
 
 template <int W, int MODE>
-__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[Geo<W>::MT][2], __amdgpu_buffer_rsrc_t rs, int voff,
+__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs, int voff,
                                            const char* br) {
-  constexpr int MT = Geo<W>::MT;
-  constexpr int NS = (MODE == kFP32) ? Geo<W>::NK8 : Geo<W>::NKB;  // even
+  constexpr int MT = Geo<W, MODE>::MT;
+  constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even
   f32x4 a0[MT], a1[MT];
   BFrag<MODE> b0, b1;
-  load_a<W>(a0, rs, voff, 0);
-  load_a<W>(a1, rs, voff, 1);
+  load_a<W, MODE>(a0, rs, voff, 0);
+  load_a<W, MODE>(a1, rs, voff, 1);
   load_b<W, MODE>(b0, br);
 #pragma unroll 1
   for (int s = 0; s < NS; s += 2) {
@@ -340,7 +361,7 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 template <int W, int MODE>
 __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {
   (void)ldb;
-  for (int f = threadIdx.x; f < W && MODE == kFP32; f += kThreads) {
+  for (int f = threadIdx.x; f < W && MODE == kFP32; f += Geo<W, MODE>::THREADS) {
     const float* a = reinterpret_cast<const float*>(act);
 #pragma unroll 4
     for (int n = 0; n < kTileQ; n += 4) {
@@ -362,7 +383,7 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const char* a = act;
     constexpr int NG = W / 8;  // feature groups
-    for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += kThreads) {
+    for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += Geo<W, MODE>::THREADS) {
       const int g8 = t % NG, nb = t / NG;
       const int gbyte = ((g8 >> 1) * 2 + (g8 & 1)) * 1024;  // 16-feature block, 8-feature half
       u32x4 m[8];
@@ -394,8 +415,9 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
 // Row-indexed vectors (b1..b4, w_out, the input-layer rows and the per-knot
 // arm term) are stored in lane-major order: the 16*MT rows one lane touches,
 // R = rbase + 32 i + 8 g + 4 h + r, sit at position
-// ((wave*2 + h)*MT + i)*16 + 4 g + r, so each lane addresses them from one base
-// with small constant offsets.
+// ((p*2 + h)*PMT + s*MT + i)*16 + 4 g + r for a wave that is share s of row
+// group p (with 4 waves, p = wave, s = 0, PMT = MT), so each lane addresses them
+// from one base with small constant offsets.
 template <int W, int MODE>
 struct Bases {
   const float* bh;    // LDS copy of b2, b3, b4 (lane-major), at this lane's block
@@ -421,9 +443,9 @@ struct TileDump {
 
 template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                           float (&sp)[2][Geo<W>::MT][2][16], float (&dpart)[2], int want_grad,
+                                           float (&sp)[2][(Geo<W, MODE>::MT)][2][16], float (&dpart)[2], int want_grad,
                                            const TileDump& td) {
-  constexpr int MT = Geo<W>::MT;
+  constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -461,7 +483,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         w5r[1] = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP + 4);
       }
       static_for<2>([&](auto NT) {
-        const float seed = b.xin[NT * 32 * Geo<W>::XIN_FLOATS + 11];
+        const float seed = b.xin[NT * 32 * Geo<W, MODE>::XIN_FLOATS + 11];
         float v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -495,8 +517,8 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
 
 template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                           const float (&sp)[2][Geo<W>::MT][2][16], const TileDump& td) {
-  constexpr int MT = Geo<W>::MT;
+                                           const float (&sp)[2][(Geo<W, MODE>::MT)][2][16], const TileDump& td) {
+  constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -529,8 +551,8 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
 template <int W, int MODE, bool PAIRS, bool TRAIN, bool SPH>
 __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
                                           float (&epart)[2][9], const TileDump& td) {
-  constexpr int MT = Geo<W>::MT;
-  constexpr int XF = Geo<W>::XIN_FLOATS;
+  constexpr int MT = Geo<W, MODE>::MT;
+  constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   f32x16 acc[MT][2];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -597,8 +619,8 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
 // Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.
 template <int W, int MODE, bool PAIRS, bool SPH>
 __device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b) {
-  constexpr int MT = Geo<W>::MT;
-  constexpr int XF = Geo<W>::XIN_FLOATS;
+  constexpr int MT = Geo<W, MODE>::MT;
+  constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
       f32x4 wa[8], wb[8];
@@ -640,27 +662,35 @@ struct TileCtx {
   char* act;
   float* xin;   // [64][16]
   float* crow;  // [W]
-  float* red;   // [4][10][64]
+  float* red;   // [waves][10][64]
   Lane<W, MODE> ln;
   Bases<W, MODE> b;
   __device__ __forceinline__ TileCtx(char* lds, const DevNet& net, int tid)
       : act(lds), ln(lds, tid) {
-    using G = Geo<W>;
+    using G = Geo<W, MODE>;
     constexpr int MT = G::MT;
     xin = reinterpret_cast<float*>(lds + G::ACT_BYTES);
     crow = xin + kTileQ * G::XIN_FLOATS;
-    red = crow + W;
-    float* vec = red + kWaves * G::RED_VALS * kTileQ;  // [4][W]: b2, b3, b4, w_out
-    for (int i = tid; i < 4 * W; i += kThreads) vec[i] = i < 3 * W ? net.bh[i] : net.w5[i - 3 * W];
-    // bytes of one matrix's fragment stream per wave (1 KiB per fragment)
-    const size_t stream_bytes = (size_t)(MODE == kFP32 ? G::NK8 : G::NKB) * MT * 1024;
-    const int lblk = (ln.wave * 2 + ln.h) * MT * 16;  // this lane's block of lane-major rows
+    float* after = crow + W;
+    if constexpr (G::RED_IN_ACT) {
+      red = reinterpret_cast<float*>(lds);
+    } else {
+      red = after;
+      after += G::RED_BYTES / 4;
+    }
+    float* vec = after;  // [4][W]: b2, b3, b4, w_out
+    for (int i = tid; i < 4 * W; i += G::THREADS) vec[i] = i < 3 * W ? net.bh[i] : net.w5[i - 3 * W];
+    // bytes of one row group's fragment stream (1 KiB per fragment, PMT per K step)
+    const size_t stream_bytes = (size_t)(MODE == kFP32 ? G::NK8 : G::NKB) * G::PMT * 1024;
+    const int pw = ln.wave / G::SUB, sub = ln.wave % G::SUB;  // row group, and this wave's share of it
+    // this lane's block of lane-major rows (see lane_major_pos: 16 PMT per (group, h))
+    const int lblk = ((pw * 2 + ln.h) * G::PMT + sub * MT) * 16;
     b.bh = vec + lblk;
     b.w5 = vec + 3 * W + lblk;
     b.w1 = net.w1p + lblk * 12;
     b.crow = crow + lblk;
     b.xin = xin + ln.n0 * G::XIN_FLOATS;
-    b.voff = (int)(ln.wave * stream_bytes) + ln.lane * 16;
+    b.voff = (int)(pw * stream_bytes) + sub * MT * 1024 + ln.lane * 16;
   }
 };
 
@@ -671,7 +701,7 @@ struct TileCtx {
 template <int W, int MODE, bool PAIRS, bool TRAIN = false, bool GATHER = false, bool SPH = false>
 __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, int want_grad, int64_t kk,
                                              int64_t q0, TileCtx<W, MODE>& tc) {
-  using G = Geo<W>;
+  using G = Geo<W, MODE>;
   constexpr int MT = G::MT;
   constexpr int XF = G::XIN_FLOATS;
   const int tid = threadIdx.x;
@@ -742,7 +772,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   }
   if constexpr (!PAIRS) {
     const float* kn = job.knots + kk * kInDim;
-    for (int r = tid; r < W; r += kThreads) {  // r: lane-major position
+    for (int r = tid; r < W; r += G::THREADS) {  // r: lane-major position
       const float* w = net.w1p + r * 12;
       crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], kn + 3);
     }
@@ -790,6 +820,9 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 #pragma unroll
     for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
   }
+  // the reduction buffer may share the activation tile: every wave must have
+  // finished reading it
+  if constexpr (G::RED_IN_ACT) __syncthreads();
   if (ln.h == 0) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -809,7 +842,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     for (int c = 0; c < G::RED_VALS; ++c) {
       float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
+      for (int w = 1; w < G::NW; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
       vals[c] = sum;
     }
     const float dv = vals[0] + *net.b5p;
@@ -852,9 +885,9 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 // One-shot kernel: a persistent grid strides over all tiles of one job.
 // ----------------------------------------------------------------------------
 template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false, bool GATHER = false, bool SPH = false>
-__global__ __launch_bounds__(kThreads, OCC) void fused_query(const DevNet net, const Job job, int want_grad,
+__global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
-  __shared__ __attribute__((aligned(16))) char lds[Geo<W>::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES];
   TileCtx<W, MODE> tc(lds, net, threadIdx.x);
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -890,7 +923,7 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   const int grid = (int)(ntiles < slots ? ntiles : slots);
   if constexpr (PAIRS && W == 256 && MODE != kBF16X2 && !SPH) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
-      hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3(kThreads), 0, s, net, job, 1,
+      hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job, 1,
                          ntiles);
       return hipGetLastError();
     }
@@ -898,12 +931,12 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   if (job.dumpH) return hipErrorInvalidValue;
   if constexpr (!PAIRS) {
     if (job.tile_off) {
-      hipLaunchKernelGGL((fused_query<W, MODE, false, OCC, false, true, SPH>), dim3(grid), dim3(kThreads), 0, s, net,
+      hipLaunchKernelGGL((fused_query<W, MODE, false, OCC, false, true, SPH>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net,
                          job, want_grad ? 1 : 0, ntiles);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC, false, false, SPH>), dim3(grid), dim3(kThreads), 0, s, net, job,
+  hipLaunchKernelGGL((fused_query<W, MODE, PAIRS, OCC, false, false, SPH>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job,
                      want_grad ? 1 : 0, ntiles);
   return hipGetLastError();
 }
