@@ -204,27 +204,55 @@ __device__ __forceinline__ void pack4(const float v[4], uint32_t& d0, uint32_t& 
 // v[4..7] for g = 2 GP + 1) of column n = 32 nt + n0.  Lane (n0, h) holds k%8 in
 // [4h, 4h+4) of both 8-groups kh = 0 (g even) and kh = 1 (g odd); one swap across
 // the lane halves gives lane (n0, kh) the whole 8-group kh, written as 16 bytes.
-template <int W, int MODE, int I, int GP, int NT>
-__device__ __forceinline__ void act_store8(const Lane<W, MODE>& L, const float v[8]) {
-  constexpr int off = (2 * I + GP) * 2048 + NT * 512;
-  auto put = [&](char* base, const float* x) {
-    uint32_t e0, e1, o0, o1;  // e: g even (kh 0), o: g odd (kh 1)
-    pack4(x, e0, e1);
-    pack4(x + 4, o0, o1);
-    // lanes 32..63 of the first operand trade with lanes 0..31 of the second:
-    // afterwards lane (n0, kh) has k%8 in [0, 4) in the first and [4, 8) in the second
+// act_pack8 forms the 16-byte words (w[0..3] for the hi plane, w[4..7] for the lo
+// plane) and act_write8 stores them, so a caller can do the arithmetic before a
+// barrier and the stores after it.
+template <int MODE>
+__device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
+  auto put = [&](const uint32_t e0, const uint32_t e1, const uint32_t o0, const uint32_t o1, uint32_t* out) {
+    // e: g even (kh 0), o: g odd (kh 1).  Lanes 32..63 of the first operand trade
+    // with lanes 0..31 of the second: afterwards lane (n0, kh) has k%8 in [0, 4)
+    // in the first and [4, 8) in the second
     const auto s0 = __builtin_amdgcn_permlane32_swap(e0, o0, false, false);
     const auto s1 = __builtin_amdgcn_permlane32_swap(e1, o1, false, false);
-    typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
-    *reinterpret_cast<u32x4*>(base + off) = u32x4{s0[0], s1[0], s0[1], s1[1]};
+    out[0] = s0[0];
+    out[1] = s1[0];
+    out[2] = s0[1];
+    out[3] = s1[1];
   };
-  put(L.act_w, v);
+  uint32_t d[4];  // bf16 pairs (v0 v1), (v2 v3), (v4 v5), (v6 v7)
+  pack4(v, d[0], d[1]);
+  pack4(v + 4, d[2], d[3]);
   if constexpr (MODE == kBF16X2) {
+    // lo = v - hi, with hi read back from the packed pairs (the same rounding);
+    // formed before the swaps, which overwrite their operands
     float lo[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) lo[r] = v[r] - (float)(__bf16)v[r];
-    put(L.act_w_lo, lo);
+    for (int k = 0; k < 4; ++k) {
+      lo[2 * k] = v[2 * k] - __uint_as_float(d[k] << 16);
+      lo[2 * k + 1] = v[2 * k + 1] - __uint_as_float(d[k] & 0xffff0000u);
+    }
+    uint32_t l[4];
+    pack4(lo, l[0], l[1]);
+    pack4(lo + 4, l[2], l[3]);
+    put(l[0], l[1], l[2], l[3], w + 4);
   }
+  put(d[0], d[1], d[2], d[3], w);
+}
+
+template <int W, int MODE, int I, int GP, int NT>
+__device__ __forceinline__ void act_write8(const Lane<W, MODE>& L, const uint32_t (&w)[8]) {
+  constexpr int off = (2 * I + GP) * 2048 + NT * 512;
+  typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+  *reinterpret_cast<u32x4*>(L.act_w + off) = u32x4{w[0], w[1], w[2], w[3]};
+  if constexpr (MODE == kBF16X2) *reinterpret_cast<u32x4*>(L.act_w_lo + off) = u32x4{w[4], w[5], w[6], w[7]};
+}
+
+template <int W, int MODE, int I, int GP, int NT>
+__device__ __forceinline__ void act_store8(const Lane<W, MODE>& L, const float v[8]) {
+  uint32_t w[8];
+  act_pack8<MODE>(v, w);
+  act_write8<W, MODE, I, GP, NT>(L, w);
 }
 
 // Either layout: rows of groups g = 2 GP, 2 GP + 1 (see act_store8).
@@ -441,6 +469,40 @@ struct TileDump {
   __device__ __forceinline__ void* g(int l) const { return static_cast<char*>(G) + l * layer_elems * elem_bytes; }
 };
 
+// Whether a hidden-layer epilogue keeps its packed results in registers across
+// the barrier (two waves per SIMD, not training).  At width 512 the last
+// forward layer, which also carries the output-layer sums, would spill, so it
+// stores after the barrier as before.
+template <int W, int MODE, bool TRAIN>
+constexpr bool defer_stores(bool last_forward) {
+  return Geo<W, MODE>::SUB > 1 && !TRAIN && (!last_forward || Geo<W, MODE>::MT == 1);
+}
+
+// The packed words of elements 8 GP .. 8 GP + 7 of an accumulator go back into
+// those elements (consumed in order, so no extra registers), and are written out
+// after the barrier.
+template <int MODE, int GP>
+__device__ __forceinline__ void park_packed(const float v[8], f32x16& a) {
+  uint32_t w[8];
+  act_pack8<MODE>(v, w);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[8 * GP + k] = __uint_as_float(w[k]);
+}
+
+template <int W, int MODE>
+__device__ __forceinline__ void write_packed(const Lane<W, MODE>& ln, const f32x16 (&acc)[(Geo<W, MODE>::MT)][2]) {
+  static_for<Geo<W, MODE>::MT>([&](auto I) {
+    static_for<2>([&](auto GP) {
+      static_for<2>([&](auto NT) {
+        uint32_t w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w[k] = __float_as_uint(acc[I][NT][8 * GP + k]);
+        act_write8<W, MODE, I, GP, NT>(ln, w);
+      });
+    });
+  });
+}
+
 template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
                                            float (&sp)[2][(Geo<W, MODE>::MT)][2][16], float (&dpart)[2], int want_grad,
@@ -458,7 +520,11 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         for (int r = 0; r < 4; ++r) acc[i][nt][4 * g + r] = b4[r];
     }
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
-  __syncthreads();
+  // With two waves per SIMD the epilogue arithmetic runs before the barrier (the
+  // results wait in registers), overlapping the K loops of waves still running;
+  // only the stores into the tile they read wait for it.
+  constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(L == 2);
+  if constexpr (!DEFER) __syncthreads();
   if constexpr (TRAIN && L == 2) {
     // training: the layer-4 activations h4 go through LDS first (for dL/dw_out)
     static_for<MT>([&](auto I) {
@@ -498,7 +564,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
             v[q] = seed * (w5r[q >> 2][q & 3] * dv);  // g4 = seed * w5 * SiLU'(z4)
           }
         }
-        if (L < 2 || want_grad) act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        if (L < 2 || want_grad) {
+          if constexpr (DEFER) park_packed<MODE, GP>(v, acc[I][NT]);
+          else act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        }
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -508,6 +577,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
     // sinks them to their use after the reverse sweep and keeps every h4 and
     // w_out value live through it.
     asm volatile("" : "+v"(dpart[0]), "+v"(dpart[1]));
+  }
+  if constexpr (DEFER) {
+    __syncthreads();  // every wave has finished reading the tile
+    if (L < 2 || want_grad) write_packed<W, MODE>(ln, acc);
   }
   __syncthreads();
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
@@ -527,7 +600,8 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
   layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
-  __syncthreads();
+  constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
+  if constexpr (!DEFER) __syncthreads();
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
       static_for<2>([&](auto NT) {
@@ -537,11 +611,16 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
           const int j = 8 * GP + q;
           v[q] = acc[I][NT][j] * unpark(sp[L - 1][I][NT][j], acc[I][NT][j]);
         }
-        act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        if constexpr (DEFER) park_packed<MODE, GP>(v, acc[I][NT]);
+        else act_store_pair<W, MODE, I, GP, NT>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
   });
+  if constexpr (DEFER) {
+    __syncthreads();  // every wave has finished reading the tile
+    write_packed<W, MODE>(ln, acc);
+  }
   __syncthreads();
   if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.g(L), td.ldb, td.q0, td.nvalid);  // g3 or g2
 }
@@ -691,6 +770,12 @@ struct TileCtx {
     b.crow = crow + lblk;
     b.xin = xin + ln.n0 * G::XIN_FLOATS;
     b.voff = (int)(pw * stream_bytes) + sub * MT * 1024 + ln.lane * 16;
+    // Two waves per SIMD: the first four waves take the matrix cores first, so
+    // they reach each layer's epilogue (vector ALU) early and run it while the
+    // other four are still in their K loops.
+    if constexpr (G::SUB > 1) {
+      if (ln.wave < kWaves) __builtin_amdgcn_s_setprio(1);
+    }
   }
 };
 
