@@ -234,7 +234,11 @@ typedef struct {
 
 /* Queue a request and return at once with its ticket.  The serving loop
  * admits queued requests while in-flight slots and the memory budget allow,
- * and runs all admitted requests' tiles in shared persistent launches.
+ * and runs all admitted requests' tiles in shared persistent launches on the
+ * library's own stream, which is not ordered after any caller stream: every
+ * write to the request's input and output buffers must have completed before
+ * the call (synchronise the streams that produce or initialise them), and the
+ * buffers must not be touched again until gcdf_poll returns GCDF_OK.
  * ENOMEM: the request alone exceeds serve_mem_budget.  EBUSY: too many queued.
  * EINVAL: bad request or serving disabled (serve_mem_budget == 0). */
 gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket);

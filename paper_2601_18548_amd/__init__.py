@@ -309,8 +309,14 @@ class Context:
 
     # -- serving ------------------------------------------------------------
     def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None) -> int:
+        """Queue a serving request.  The serving loop runs on the library's own
+        stream, so the current torch stream (which may still be producing the
+        inputs or initialising the outputs) is synchronised first."""
+        import torch
+
         if points.dim() != 2 or points.shape[1] != self.obstacle_dim:
             raise ValueError("points must be (Np, %d)" % self.obstacle_dim)
+        torch.cuda.current_stream(knots.device).synchronize()
         req = _Request()
         req.knots, req.K = knots.data_ptr(), knots.shape[0]
         req.points, req.Np = points.data_ptr(), points.shape[0]

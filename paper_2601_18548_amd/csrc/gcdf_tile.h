@@ -1013,7 +1013,7 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
       return hipGetLastError();
     }
   }
-  if (job.dumpH) return hipErrorInvalidValue;
+  if (job.dumpH || job.seed) return hipErrorInvalidValue;  // a seed is honoured by the training instantiation only
   if constexpr (!PAIRS) {
     if (job.tile_off) {
       hipLaunchKernelGGL((fused_query<W, MODE, false, OCC, false, true, SPH>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net,
