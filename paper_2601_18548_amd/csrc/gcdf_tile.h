@@ -132,6 +132,10 @@ struct Geo {
   // not leave room for it (the tile is idle by then)
   static constexpr bool RED_IN_ACT = NW > kWaves;
   static constexpr int NKB = W / 16;                 // 16-deep K blocks (bf16)
+  // bytes of the activation tile per K step (16 rows in the BF16 modes, 8 in FP32);
+  // BF16X2 keeps a step's hi and lo halves next to each other, lo at LO_OFF
+  static constexpr int STEP_BYTES = MODE == kBF16X2 ? 4096 : 2048;
+  static constexpr int LO_OFF = 2048;
   static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
   static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
   static constexpr int XIN_FLOATS = 17;              // per query: p'(3), cos, sin, arm(6), seed, radius, pad; odd stride: lanes reading one field of 32 queries hit 32 different banks
@@ -144,11 +148,13 @@ struct Geo {
 
 // ----------------------------------------------------------------------------
 // Activation tile in LDS (64 query columns).
-//  bf16 modes: hi plane then lo plane (W*128 bytes each).  Element (k, n) sits in
-//    the 16-byte group (k/16, (k%16)/8, n) at byte ((k/16)*2 + (k%16)/8)*1024 + n*16,
-//    position k%8 inside it.  The B fragment of K step s, column block nt is the
-//    2 KiB at s*2048, lane (n0, kh) reading the 16 bytes at kh*1024 + nt*512 + n0*16:
-//    every lane reads its own consecutive 16 bytes (no bank conflicts).
+//  bf16 modes: K step s (rows 16s .. 16s+15) occupies STEP_BYTES at s*STEP_BYTES:
+//    its hi half, then (BF16X2) its lo half at +LO_OFF, so one base register with
+//    small immediate offsets reaches both.  Element (k, n) of a half sits in the
+//    16-byte group ((k%16)/8, n) at byte ((k%16)/8)*1024 + n*16, position k%8
+//    inside it.  The B fragment of step s, column block nt is the 2 KiB half, lane
+//    (n0, kh) reading the 16 bytes at kh*1024 + nt*512 + n0*16: every lane reads
+//    its own consecutive 16 bytes (no bank conflicts).
 //  fp32 mode : element (k, n) at (((k/8)*64 + n)*2 + k%2)*4 + (k%8)/2 floats; the
 //    B fragment of step s, block nt starts at s*2048 + nt*1024, lane (n0, kh) at
 //    +n0*32 + kh*16.
@@ -175,10 +181,10 @@ struct Lane {
       act_w = act + 4 * (((rbase >> 3) * kTileQ + n0) * 8 + 2 * h);
       act_r = act + n0 * 32 + kh * 16;
     } else {
-      act_w = act + (rbase >> 4) * 2048 + h * 1024 + n0 * 16;
+      act_w = act + (rbase >> 4) * Geo<W, MODE>::STEP_BYTES + h * 1024 + n0 * 16;
       act_r = act + kh * 1024 + n0 * 16;
     }
-    act_w_lo = act_w + W * kTileQ * 2;
+    act_w_lo = act_w + Geo<W, MODE>::LO_OFF;
   }
 };
 
@@ -242,7 +248,7 @@ __device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
 
 template <int W, int MODE, int I, int GP, int NT>
 __device__ __forceinline__ void act_write8(const Lane<W, MODE>& L, const uint32_t (&w)[8]) {
-  constexpr int off = (2 * I + GP) * 2048 + NT * 512;
+  constexpr int off = (2 * I + GP) * Geo<W, MODE>::STEP_BYTES + NT * 512;
   typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
   *reinterpret_cast<u32x4*>(L.act_w + off) = u32x4{w[0], w[1], w[2], w[3]};
   if constexpr (MODE == kBF16X2) *reinterpret_cast<u32x4*>(L.act_w_lo + off) = u32x4{w[4], w[5], w[6], w[7]};
@@ -299,7 +305,7 @@ __device__ __forceinline__ void load_b(BFrag<MODE>& b, const char* br) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       b.h[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 512);
-      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + W * kTileQ * 2 + nt * 512);
+      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + Geo<W, MODE>::LO_OFF + nt * 512);
     }
   }
 }
@@ -357,6 +363,7 @@ __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2],
                                            const char* br) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even
+  constexpr int SB = Geo<W, MODE>::STEP_BYTES;
   f32x4 a0[MT], a1[MT];
   BFrag<MODE> b0, b1;
   load_a<W, MODE>(a0, rs, voff, 0);
@@ -364,13 +371,13 @@ __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2],
   load_b<W, MODE>(b0, br);
 #pragma unroll 1
   for (int s = 0; s < NS; s += 2) {
-    load_b<W, MODE>(b1, br + 2048);  // B of step s+1, one step ahead
+    load_b<W, MODE>(b1, br + SB);  // B of step s+1, one step ahead
     __builtin_amdgcn_sched_barrier(0);
     mma_step_reload<W, MODE>(acc, a0, b0, rs, voff, s + 2 < NS ? s + 2 : NS - 1);
-    load_b<W, MODE>(b0, s + 2 < NS ? br + 4096 : br);  // B of step s+2
+    load_b<W, MODE>(b0, s + 2 < NS ? br + 2 * SB : br);  // B of step s+2
     __builtin_amdgcn_sched_barrier(0);
     mma_step_reload<W, MODE>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
-    br += 4096;
+    br += 2 * SB;
   }
 }
 
@@ -413,7 +420,7 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
     constexpr int NG = W / 8;  // feature groups
     for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += Geo<W, MODE>::THREADS) {
       const int g8 = t % NG, nb = t / NG;
-      const int gbyte = ((g8 >> 1) * 2 + (g8 & 1)) * 1024;  // 16-feature block, 8-feature half
+      const int gbyte = (g8 >> 1) * Geo<W, MODE>::STEP_BYTES + (g8 & 1) * 1024;  // 16-feature step, 8-feature half
       u32x4 m[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -921,7 +928,10 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 
   // ---- per query: final sums, chain rule, stores, per-knot minimum ----
   if (tid < kTileQ) {
-    const int n = tid;
+    // recomputed here rather than kept from the prologue (the compiler would
+    // otherwise hold q0 + tid through the whole tile, in a spill slot)
+    int n = tid;
+    asm volatile("" : "+v"(n));
     float vals[G::RED_VALS];
 #pragma unroll
     for (int c = 0; c < G::RED_VALS; ++c) {

@@ -157,3 +157,22 @@ def test_serving_disabled_rejects_submit(gcdf, weights):
     ctx = gcdf.Context(weights.to_blob(), 256, "bf16x2")
     with pytest.raises(gcdf.GcdfError):
         Req(16, 512, 50).submit(ctx)
+
+
+@pytest.mark.parametrize("width,precision", [(512, "bf16x2"), (512, "bf16"), (512, "fp32"), (256, "fp32")])
+def test_other_widths_and_precisions_match_one_shot(gcdf, width, precision):
+    """Serving instantiations beyond the benchmark's (width 512 runs 8 waves in the
+    BF16 modes, FP32 runs 4): bitwise equal to the one-shot query, including a
+    request that arrives after the loop went idle and exited (relaunch)."""
+    w = wl.weights(width, seed=22)
+    srv = gcdf.Context(w.to_blob(), width, precision, serve_mem_budget=2 * GiB, serve_slots=4)
+    one = gcdf.Context(w.to_blob(), width, precision)
+    first = [Req(9, 700, 60), Req(5, 130, 61)]
+    wait_all(srv, [r.submit(srv) for r in first])
+    time.sleep(0.02)  # well past the 2 ms idle exit
+    late = Req(12, 1000, 62)
+    wait_all(srv, [late.submit(srv)])
+    for r in first + [late]:
+        for a, b in zip(r.arrays(), reference(one, r)):
+            assert np.array_equal(a, b)
+    srv.close()
