@@ -44,9 +44,17 @@ def flops_per_pair(width: int) -> int:
     return 12 * width * width + 38 * width
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(text: str | None = None) -> str:
+    """Hash of the query kernel's code with comments and blank space removed, so
+    that a comment edit does not orphan counters taken on unchanged code."""
+    import re
+
+    if text is None:
+        with open(KERNEL_SRC) as f:
+            text = f.read()
+    code = re.sub(r"//[^\n]*", "", text)
+    code = "\n".join(" ".join(line.split()) for line in code.splitlines() if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic(launch_pairs: int):
@@ -57,7 +65,7 @@ def measured_traffic(launch_pairs: int):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("pairs_per_launch") != launch_pairs:
+    if t.get("kernel_code_sha256_16") != kernel_source_hash() or t.get("pairs_per_launch") != launch_pairs:
         return None
     return t.get("hbm_bytes_per_launch")
 

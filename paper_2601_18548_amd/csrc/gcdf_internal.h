@@ -8,7 +8,7 @@ namespace gcdf {
 constexpr int kInDim = 9;         // configuration coordinates per knot (x, y, yaw, a1..a6)
 constexpr int kInDimSphere = 10;  // network inputs for sphere obstacles: [p', r, a]
 constexpr int kTileQ = 64;   // queries per tile (two 32-wide MFMA column blocks)
-constexpr int kWaves = 4;    // waves per workgroup, one per SIMD
+constexpr int kWaves = 4;    // row groups of the packed weights; waves per workgroup in FP32 (BF16: 8)
 constexpr int kThreads = 64 * kWaves;
 
 enum Mode : int { kFP32 = 0, kBF16 = 1, kBF16X2 = 2 };

@@ -1,8 +1,9 @@
 // Tile engine of the fused batched neural-GCDF query for gfx950 (MI355X):
 // device code shared by the query, sphere-query and serving kernels.
 //
-// One workgroup (4 waves, one per SIMD) owns a tile of 64 queries: 64 points
-// of one knot (dense all-pairs mode) or 64 entries of a pair list.  For the
+// One workgroup (8 waves, two per SIMD, in the BF16 modes; 4 in FP32) owns a
+// tile of 64 queries: 64 points of one knot (dense all-pairs mode) or 64
+// entries of a pair list.  For the
 // tile it runs the whole query without touching HBM in between:
 //   base-frame transform -> input layer (FP32, VALU) -> hidden layers on
 //   matrix cores -> output dot -> reverse sweep on matrix cores (transposed
@@ -14,9 +15,9 @@
 //
 // Work split inside the tile: every hidden layer is C[W x 64] = M[W x W] B[W x 64]
 // with M = W_l (forward) or W_l^T (reverse) and B = the previous layer's
-// activations (forward) or back-propagated gradients (reverse).  Wave w owns
-// output rows [w*W/4, (w+1)*W/4) for all 64 queries; B lives in LDS (written by
-// the epilogue of the previous layer, read by all four waves); the A fragments
+// activations (forward) or back-propagated gradients (reverse).  With n waves,
+// wave w owns output rows [w*W/n, (w+1)*W/n) for all 64 queries; B lives in LDS
+// (written by the epilogue of the previous layer, read by every wave); the A fragments
 // stream from global memory (L2-resident, pre-packed so each 32x16 fragment is
 // one contiguous 1 KiB block: one dwordx4 per lane).  Each weight byte fetched
 // is used for 64 queries.
@@ -284,10 +285,11 @@ __device__ __forceinline__ void static_for(F&& f) {
 // ----------------------------------------------------------------------------
 // acc[i][nt] += M[rows of wave, :] x act[:, 32nt .. 32nt+31]
 // A fragments come through a buffer descriptor (uniform, SGPRs) of the matrix's
-// packed stream: fragment (kstep, i) of this wave at byte
-// wave*stream_bytes + ((kstep*MT + i)*64 + lane)*16 -- one 32-bit VGPR offset
-// (voff = wave*stream_bytes + lane*16) serves every matrix and step; the step goes
-// in the scalar offset and i*1024 in the instruction's immediate.
+// packed stream, laid out for 4 row groups of PMT M tiles: fragment (kstep, j) of
+// row group p at byte p*stream_bytes + ((kstep*PMT + j)*64 + lane)*16.  A wave
+// that is share s of group p reads j = s*MT + i, so one 32-bit VGPR offset
+// (voff = p*stream_bytes + s*MT*1024 + lane*16) serves every matrix and step; the
+// step goes in the scalar offset and i*1024 in the instruction's immediate.
 // Software pipeline: A is loaded two K steps ahead, B (LDS) one step ahead.
 // ----------------------------------------------------------------------------
 template <int MODE>
@@ -460,7 +462,7 @@ struct Bases {
   const float* w1;    // input layer rows (lane-major, 12 floats per row), at this lane's block
   const float* crow;  // per-knot input-layer constant (LDS, lane-major), at this lane's block
   const float* xin;   // xin + n0 * XIN_FLOATS
-  int voff;           // lane offset inside a matrix's fragment stream: wave*stream_bytes + lane*16
+  int voff;           // lane offset inside a matrix's fragment stream (see load_a)
 };
 
 // Dump of the current LDS tile for training (no-op when not training).
