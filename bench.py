@@ -12,7 +12,7 @@ Prints one JSON line: pairs (queries) per second, plus
   roofline     : the fused kernel's algorithmic TFLOP/s vs the dense BF16 peak
                  (launch durations from HIP events on the launch stream);
   cpu_baseline : the FP64 CPU oracle on a bounded sample of the same pairs;
-  modes        : the same workload in FP32 and pure BF16 (context, same metric);
+  modes        : the same workload in the other precisions (context, same metric);
   serving      : p50 / p99 latency of a Poisson request trace through gcdf_submit;
   constraints  : partitions around a 128-knot trajectory, the CSR query, the
                  Jacobian pattern and the single-step projection (HBM roofline);
@@ -31,7 +31,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"bf16x2": 2500.0, "bf16": 2500.0, "fp32": 157.3}
+PEAK_TFLOPS = {"bf16x2": 2500.0, "bf16x2_f16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
+DESCRIBE = {
+    "bf16x2": "BF16 matrix cores, hi/lo split activations, FP32 accumulate",
+    "bf16x2_f16": "BF16 matrix cores with hi/lo split activations forward, FP16 matrix cores for the reverse sweep, FP32 accumulate",
+}
+MEETS_BAR = {"fp32": True, "bf16x2": True, "bf16x2_f16": True, "bf16": False}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_query_bf16_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_18548_amd", "csrc", "gcdf_tile.h")  # the query kernel's code
 
@@ -57,15 +62,17 @@ def kernel_source_hash(text: str | None = None) -> str:
     return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def measured_traffic(launch_pairs: int):
+def measured_traffic(launch_pairs: int, precision: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None if the
-    kernel source changed since the counters were taken."""
+    kernel code changed since the counters were taken or they cover another
+    launch size or precision."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_code_sha256_16") != kernel_source_hash() or t.get("pairs_per_launch") != launch_pairs:
+    if (t.get("kernel_code_sha256_16") != kernel_source_hash() or t.get("pairs_per_launch") != launch_pairs
+            or t.get("precision") != precision):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -100,7 +107,7 @@ def time_mode(g, torch, wk, precision, steps, warmup):
     return dt, kms
 
 
-def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precision: str = "bf16x2",
+def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precision: str = "bf16x2_f16",
                 budget_gib: float = 16.0, slots: int = 64, ring: int = 128):
     """Poisson stream of trajectory-optimisation requests through gcdf_submit/gcdf_poll.
 
@@ -225,7 +232,7 @@ def constraints_bench(g, torch, wk, reps: int = 5, n_knots: int = 128, radius: f
 
 def sphere_bench(g, torch, point_kernel_ms: float, reps: int = 10):
     """Sphere obstacles (x, y, z, r) with the 10-input network [p', r, a]: the
-    benchmark shape (128 knots x 16,384 spheres, width 512, BF16X2), one fused
+    benchmark shape (128 knots x 16,384 spheres, width 512, its precision), one fused
     eval_grad launch per rep, timed with HIP events on its stream."""
     from paper_2601_18548_amd import workloads as wl
 
@@ -244,8 +251,8 @@ def sphere_bench(g, torch, point_kernel_ms: float, reps: int = 10):
     fl = (12 * wk.width * wk.width + 40 * wk.width) * pairs
     tf = fl / (ms * 1e-3) / 1e12
     ctx.close()
-    return {"workload": "128 knots x 16384 spheres (x, y, z, r), width 512, bf16x2, input [p', r, a]",
-            "kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS["bf16x2"],
+    return {"workload": "128 knots x 16384 spheres (x, y, z, r), width 512, %s, input [p', r, a]" % wk.precision,
+            "kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "tflops": tf, "frac_of_peak": tf / PEAK_TFLOPS[wk.precision],
             "vs_point_kernel": point_kernel_ms / ms}
 
 
@@ -358,9 +365,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bf16", choices=["bf16", "fp32", "small"])
+    ap.add_argument("--precision", default=None, choices=sorted(PEAK_TFLOPS),
+                    help="precision of the timed query (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-modes", action="store_true", help="skip the FP32 / pure-BF16 context runs")
+    ap.add_argument("--no-modes", action="store_true", help="skip the runs of the workload in the other precisions")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -396,6 +405,8 @@ def main():
             print(json.dumps({"serving": serve_bench(g, torch, rate, args.serve_requests)}), flush=True)
         return
     wk = wl.workload(args.workload)
+    if args.precision:
+        wk.precision = args.precision
     pairs = wk.K * wk.Np
     print("bench: workload %s (%d knots x %d points, width %d, %s), %d steps after %d warmup" %
           (args.workload, wk.K, wk.Np, wk.width, wk.precision, args.steps, args.warmup), file=sys.stderr, flush=True)
@@ -417,12 +428,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if wk.precision.startswith("bf16") else "fp32",
+        "dtype": {"bf16x2_f16": "bf16x2 fwd / f16 rev", "bf16x2": "bf16x2"}.get(wk.precision, wk.precision),
         "data": "synthetic (seeded knots, patch point clouds, He-normal random weights)",
         "config": {
             "workload": "%d knots x %d points, distance MLP 9->%dx4->1 SiLU, %s" %
-                        (wk.K, wk.Np, wk.width, "BF16 matrix cores, hi/lo split activations, FP32 accumulate"
-                         if wk.precision == "bf16x2" else wk.precision),
+                        (wk.K, wk.Np, wk.width, DESCRIBE.get(wk.precision, wk.precision)),
             "knots": wk.K, "points": wk.Np, "width": wk.width, "precision": wk.precision,
             "pairs_per_step": pairs, "outputs": "d, J (9 per pair), per-knot min + argmin",
         },
@@ -432,19 +442,20 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(pairs),
+            "traffic": measured_traffic(pairs, wk.precision),
             "kernel": "fused_query (one launch = %d pairs x %d FLOP)" % (pairs, flops_per_pair(wk.width)),
             "kernel_ms": kernel_ms,
         },
     }
     if not args.no_modes and args.workload == "bf16":
         modes = {}
-        for prec, st in (("fp32", 3), ("bf16", args.steps)):
+        others = [p for p in ("bf16x2", "bf16x2_f16") if p != wk.precision]
+        for prec, st in [("fp32", 3), ("bf16", args.steps)] + [(p, args.steps) for p in others]:
             s, kms = time_mode(g, torch, wk, prec, st, 1)
             a = flops_per_pair(wk.width) * pairs / (kms * 1e-3) / 1e12
             modes[prec] = {"queries_per_s": pairs / s, "kernel_ms": kms, "tflops": a,
                            "frac_of_peak": a / PEAK_TFLOPS[prec], "peak": PEAK_TFLOPS[prec],
-                           "meets_1e-3": prec == "fp32"}
+                           "meets_1e-3": MEETS_BAR[prec]}
             print("bench: mode %s %.3f ms/step" % (prec, s * 1e3), file=sys.stderr, flush=True)
         # the FP32 configuration at its own shape: 64 knots x 4,096 points, width 256
         wk2 = wl.workload("fp32")

@@ -69,7 +69,12 @@ typedef enum {
 typedef enum {
     GCDF_FP32 = 0,   /* all layers in FP32 (matrix cores, FP32 in and out) */
     GCDF_BF16 = 1,   /* hidden layers on BF16 matrix cores, FP32 accumulate (fast; ~1e-2 error) */
-    GCDF_BF16X2 = 2  /* as BF16 with each activation split into hi + lo BF16 parts (FP32-class error) */
+    GCDF_BF16X2 = 2, /* as BF16 with each activation split into hi + lo BF16 parts (FP32-class error) */
+    GCDF_BF16X2_F16 = 3 /* forward layers as BF16X2; the reverse sweep multiplies FP16 back-propagated
+                         * values (scaled by 2^6) by the BF16-rounded transposed weights held as FP16:
+                         * one product instead of two per reverse fragment, d as BF16X2, Jacobian
+                         * relative error ~1e-3.  Hidden weights must satisfy |w| < 65408; values
+                         * back-propagated beyond ~1e3 in magnitude overflow FP16 */
 } gcdf_precision;
 
 typedef struct {
@@ -93,8 +98,11 @@ typedef struct gcdf_ctx gcdf_ctx;
  * w_out (1 x width), b_out, each matrix row-major (out x in) -- the network of
  * Sec. III-C.  For the BF16 precisions W2..W_depth are rounded to BF16
  * (round-to-nearest-even); blobs whose hidden matrices already lie on the BF16
- * grid are multiplied exactly.  Errors: EINVAL (bad config or blob: width not
- * 256/512, depth != 4, in_dim not 9 or 10, size mismatch), ENOMEM, EDEVICE. */
+ * grid are multiplied exactly (GCDF_BF16X2_F16: also in FP16, for |w| >= 2^-17;
+ * smaller weights round by at most 2^-25).  Errors: EINVAL (bad config or blob:
+ * width not 256/512, depth != 4, in_dim not 9 or 10, size mismatch; for
+ * GCDF_BF16X2_F16 a hidden weight with |w| >= 65408 or not finite), ENOMEM,
+ * EDEVICE. */
 gcdf_status gcdf_create(const gcdf_config* cfg, const void* weight_blob, size_t blob_bytes, gcdf_ctx** out);
 
 /* Destroy a context: waits for in-flight serving requests, then frees every

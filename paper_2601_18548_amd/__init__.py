@@ -17,8 +17,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgcdf.so")
 
-FP32, BF16, BF16X2 = 0, 1, 2
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16x2": BF16X2}
+FP32, BF16, BF16X2, BF16X2_F16 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16x2": BF16X2, "bf16x2_f16": BF16X2_F16}
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "OK", 1: "PENDING", 2: "EINVAL", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUSY"}
 

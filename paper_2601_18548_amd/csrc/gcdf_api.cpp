@@ -2,6 +2,7 @@
 // The query semantics are documented in include/gcdf.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -95,7 +96,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   *out = nullptr;
   if (cfg->width != 256 && cfg->width != 512) return fail(GCDF_EINVAL, "width must be 256 or 512 (got %d)", cfg->width);
   if (cfg->depth != 4) return fail(GCDF_EINVAL, "depth must be 4 (got %d)", cfg->depth);
-  if (cfg->precision < GCDF_FP32 || cfg->precision > GCDF_BF16X2)
+  if (cfg->precision < GCDF_FP32 || cfg->precision > GCDF_BF16X2_F16)
     return fail(GCDF_EINVAL, "unknown precision %d", cfg->precision);
   if (cfg->max_knots < 0) return fail(GCDF_EINVAL, "max_knots must be >= 0");
   const int W = cfg->width;
@@ -109,6 +110,18 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   // blob: header + W1, b1, (W2, b2) .. (W4, b4), w_out, b_out
   const size_t nfloat = (size_t)W * in_dim + W + 3 * ((size_t)W * W + W) + W + 1;
   if (bytes != kHeader + 4 * nfloat) return fail(GCDF_EINVAL, "weight blob is %zu bytes, expected %zu", bytes, kHeader + 4 * nfloat);
+  if (cfg->precision == GCDF_BF16X2_F16) {
+    // The reverse sweep holds the BF16-rounded hidden weights as FP16: every one
+    // must round to a finite FP16 value (|w| < 65408 rounds to at most 65280).
+    const char* p = static_cast<const char*>(blob) + kHeader + 4 * ((size_t)W * in_dim + W);
+    for (int l = 0; l < 3; ++l, p += 4 * ((size_t)W * W + W))
+      for (size_t i = 0; i < (size_t)W * W; ++i) {
+        float v;
+        std::memcpy(&v, p + 4 * i, 4);
+        if (!(std::fabs(v) < 65408.0f))
+          return fail(GCDF_EINVAL, "precision BF16X2_F16: hidden weight W%d[%zu] = %g is not finite in FP16", l + 2, i, (double)v);
+      }
+  }
 
   int dev = cfg->device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(GCDF_EDEVICE, "no current HIP device");

@@ -175,7 +175,7 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
 #pragma unroll
             for (int r = 0; r < 4; ++r) a[i][nt][4 * g + r] = b4[r];
         }
-      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+      layer_gemm<W, MODE, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
       __syncthreads();
       put_all(sZ + (L + 1) * arr, a);
       emit(a, nullptr, nullptr, nullptr, [&](int, int, int, float acc, float, float, float) { return silu_only(acc); });
@@ -194,7 +194,7 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
     static_for<3>([&](auto LL) {
       constexpr int L = 2 - LL;  // W_{L+2}^T g_{L+2} = r_{L+1}
       zero(a);
-      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+      layer_gemm<W, MODE, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
       __syncthreads();
       put_all(sR + L * arr, a);
       emit(a, sZ + L * arr, nullptr, nullptr, [&](int, int, int, float acc, float z, float, float) {
@@ -251,7 +251,7 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
     static_for<3>([&](auto L) {
       // zdot_{L+2} = W_{L+2} hdot_{L+1}; hdot_{L+2} = s'(z_{L+2}) zdot_{L+2}
       zero(a);
-      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+      layer_gemm<W, MODE, MODE>(a, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
       __syncthreads();
       put_all(sZd + (L + 1) * arr, a);
       emit(a, sZ + (L + 1) * arr, nullptr, nullptr, [&](int, int, int, float acc, float z, float, float) {
@@ -276,7 +276,7 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
     static_for<3>([&](auto LL) {
       constexpr int L = 2 - LL;  // hbar_{L+1} = W_{L+2}^T zbar_{L+2}
       zero(a);
-      layer_gemm<W, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+      layer_gemm<W, MODE, MODE>(a, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
       __syncthreads();
       emit(a, sZ + L * arr, sZd + L * arr, sR + L * arr, [&](int, int, int, float hb, float z, float zd, float r) {
         float d1, d2;
@@ -399,7 +399,10 @@ size_t packed_matrix_bytes(int width, int mode) {
 }
 
 // Output element -> source element.  Chunk order: [wave][kstep][i] with 64 lanes per chunk.
-__global__ void pack_bf16_kernel(const float* __restrict__ src, __bf16* __restrict__ dst, int W, int transpose) {
+// Elements are rounded to BF16; with to_f16 the BF16 value is then stored as FP16
+// (exact for magnitudes in [2^-17, 65504], the range gcdf_create admits).
+__global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int W, int transpose,
+                                 int to_f16) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)W * W) return;
   const int MT = W / (32 * kWaves), NKB = W / 16;
@@ -412,7 +415,8 @@ __global__ void pack_bf16_kernel(const float* __restrict__ src, __bf16* __restri
   const int row = 32 * (wave * MT + i) + (lane & 31);
   const int col = 16 * kb + 8 * (lane >> 5) + e;
   const float v = transpose ? src[(int64_t)col * W + row] : src[(int64_t)row * W + col];
-  dst[idx] = (__bf16)v;
+  const __bf16 vb = (__bf16)v;
+  dst[idx] = to_f16 ? __builtin_bit_cast(uint16_t, (_Float16)(float)vb) : __builtin_bit_cast(uint16_t, vb);
 }
 
 __global__ void pack_fp32_kernel(const float* __restrict__ src, float* __restrict__ dst, int W, int transpose) {
@@ -437,9 +441,9 @@ hipError_t pack_matrix(const float* src, void* dst, int width, int mode, bool tr
   if (mode == kFP32)
     hipLaunchKernelGGL(pack_fp32_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<float*>(dst), width,
                        transpose ? 1 : 0);
-  else
-    hipLaunchKernelGGL(pack_bf16_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<__bf16*>(dst), width,
-                       transpose ? 1 : 0);
+  else  // the reverse sweep of kBF16X2F16 multiplies the transposed matrix in FP16
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<uint16_t*>(dst), width,
+                       transpose ? 1 : 0, (transpose && mode == kBF16X2F16) ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -11,7 +11,9 @@ constexpr int kTileQ = 64;   // queries per tile (two 32-wide MFMA column blocks
 constexpr int kWaves = 4;    // row groups of the packed weights; waves per workgroup in FP32 (BF16: 8)
 constexpr int kThreads = 64 * kWaves;
 
-enum Mode : int { kFP32 = 0, kBF16 = 1, kBF16X2 = 2 };
+// kBF16X2F16: forward layers as kBF16X2, reverse sweep as single-pass FP16
+// products (transposed weights packed in FP16).
+enum Mode : int { kFP32 = 0, kBF16 = 1, kBF16X2 = 2, kBF16X2F16 = 3 };
 
 // Device-resident network in kernel layout.
 // Row-indexed arrays are in the kernel's lane-major row order (pack_input_layer,

@@ -225,12 +225,14 @@ static hipError_t launch_serve_k(const DevNet& net, ServeCtl* ctl, ServeDev* dev
     switch (net.mode) {
       case kFP32: return launch_serve_t<256, kFP32, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
       case kBF16: return launch_serve_t<256, kBF16, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+      case kBF16X2F16: return launch_serve_t<256, kBF16X2F16, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
       default: return launch_serve_t<256, kBF16X2, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
     }
   }
   switch (net.mode) {
     case kFP32: return launch_serve_t<512, kFP32, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
     case kBF16: return launch_serve_t<512, kBF16, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
+    case kBF16X2F16: return launch_serve_t<512, kBF16X2F16, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
     default: return launch_serve_t<512, kBF16X2, SPH>(net, ctl, dev, first_seq, idle_ticks, epoch, num_cu, s);
   }
 }

@@ -28,6 +28,10 @@
 //   BF16X2 : as BF16 but each activation is split x = hi + lo (both BF16) and both
 //            halves are multiplied (2 MFMAs per fragment pair); hidden weights must
 //            lie on the BF16 grid to be exact.
+//   BF16X2F16 : forward layers as BF16X2; the reverse sweep multiplies FP16
+//            back-propagated values by the FP16 copy of the transposed BF16 weights
+//            (v_mfma_f32_32x32x16_f16, one MFMA per fragment pair), the values
+//            scaled by 2^6 to keep them in FP16's normal range.
 // The SiLU derivative needed by the reverse sweep is kept in FP32 registers for
 // layers 2 and 3 and recomputed for layer 1 from the input layer.
 #pragma once
@@ -45,6 +49,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(_Float16)))) _Float16 f16x4;
 
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -119,6 +125,26 @@ constexpr int waves_for() {
   return MODE != kFP32 ? 8 : 4;
 }
 
+// Arithmetic of one K loop and of the LDS stores that feed it.  Every mode
+// uses its own throughout, except kBF16X2F16: BF16X2 forward, and kF16 (single
+// FP16 products; an arithmetic kind, never a context mode) in the reverse sweep.
+constexpr int kF16 = 4;
+template <int MODE>
+constexpr int fwd_arith() {
+  return MODE == kBF16X2F16 ? kBF16X2 : MODE;
+}
+template <int MODE>
+constexpr int rev_arith() {
+  return MODE == kBF16X2F16 ? kF16 : MODE;
+}
+// Scale of the reverse sweep's seed (kBF16X2F16): back-propagated values between
+// ~1e-6 and ~1e3 stay normal FP16 numbers; the input-layer gradient is
+// multiplied back by its inverse.  Powers of two, so both steps are exact.
+template <int MODE>
+constexpr float rev_scale() {
+  return MODE == kBF16X2F16 ? 64.0f : 1.0f;
+}
+
 template <int W, int MODE>
 struct Geo {
   static constexpr int NW = waves_for<W, MODE>();    // waves per workgroup
@@ -135,7 +161,7 @@ struct Geo {
   static constexpr int NKB = W / 16;                 // 16-deep K blocks (bf16)
   // bytes of the activation tile per K step (16 rows in the BF16 modes, 8 in FP32);
   // BF16X2 keeps a step's hi and lo halves next to each other, lo at LO_OFF
-  static constexpr int STEP_BYTES = MODE == kBF16X2 ? 4096 : 2048;
+  static constexpr int STEP_BYTES = fwd_arith<MODE>() == kBF16X2 ? 4096 : 2048;
   static constexpr int LO_OFF = 2048;
   static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
   static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
@@ -197,12 +223,21 @@ __device__ __forceinline__ void act_store4_fp32(const Lane<W, MODE>& L, const fl
   *reinterpret_cast<f32x2*>(L.act_w + off + 16) = f32x2{v[1], v[3]};  // rows R0+1, R0+3 (k%2 = 1)
 }
 
-// Pack four floats into two dwords of bf16 (round to nearest even).
+// Pack four floats into two dwords of bf16 (FP16 for kF16), round to nearest even.
+template <int AM>
 __device__ __forceinline__ void pack4(const float v[4], uint32_t& d0, uint32_t& d1) {
-  bf16x4 h4;
+  f32x2 d;
+  if constexpr (AM == kF16) {
+    f16x4 h4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) h4[r] = (__bf16)v[r];
-  const f32x2 d = __builtin_bit_cast(f32x2, h4);
+    for (int r = 0; r < 4; ++r) h4[r] = (_Float16)v[r];
+    d = __builtin_bit_cast(f32x2, h4);
+  } else {
+    bf16x4 h4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h4[r] = (__bf16)v[r];
+    d = __builtin_bit_cast(f32x2, h4);
+  }
   d0 = __float_as_uint(d[0]);
   d1 = __float_as_uint(d[1]);
 }
@@ -213,8 +248,8 @@ __device__ __forceinline__ void pack4(const float v[4], uint32_t& d0, uint32_t& 
 // the lane halves gives lane (n0, kh) the whole 8-group kh, written as 16 bytes.
 // act_pack8 forms the 16-byte words (w[0..3] for the hi plane, w[4..7] for the lo
 // plane) and act_write8 stores them, so a caller can do the arithmetic before a
-// barrier and the stores after it.
-template <int MODE>
+// barrier and the stores after it.  AM: the arithmetic (fwd_arith / rev_arith).
+template <int AM>
 __device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
   auto put = [&](const uint32_t e0, const uint32_t e1, const uint32_t o0, const uint32_t o1, uint32_t* out) {
     // e: g even (kh 0), o: g odd (kh 1).  Lanes 32..63 of the first operand trade
@@ -228,9 +263,9 @@ __device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
     out[3] = s1[1];
   };
   uint32_t d[4];  // bf16 pairs (v0 v1), (v2 v3), (v4 v5), (v6 v7)
-  pack4(v, d[0], d[1]);
-  pack4(v + 4, d[2], d[3]);
-  if constexpr (MODE == kBF16X2) {
+  pack4<AM>(v, d[0], d[1]);
+  pack4<AM>(v + 4, d[2], d[3]);
+  if constexpr (AM == kBF16X2) {
     // lo = v - hi, with hi read back from the packed pairs (the same rounding);
     // formed before the swaps, which overwrite their operands
     float lo[8];
@@ -240,36 +275,36 @@ __device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
       lo[2 * k + 1] = v[2 * k + 1] - __uint_as_float(d[k] & 0xffff0000u);
     }
     uint32_t l[4];
-    pack4(lo, l[0], l[1]);
-    pack4(lo + 4, l[2], l[3]);
+    pack4<AM>(lo, l[0], l[1]);
+    pack4<AM>(lo + 4, l[2], l[3]);
     put(l[0], l[1], l[2], l[3], w + 4);
   }
   put(d[0], d[1], d[2], d[3], w);
 }
 
-template <int W, int MODE, int I, int GP, int NT>
+template <int W, int MODE, int I, int GP, int NT, int AM = fwd_arith<MODE>()>
 __device__ __forceinline__ void act_write8(const Lane<W, MODE>& L, const uint32_t (&w)[8]) {
   constexpr int off = (2 * I + GP) * Geo<W, MODE>::STEP_BYTES + NT * 512;
   typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
   *reinterpret_cast<u32x4*>(L.act_w + off) = u32x4{w[0], w[1], w[2], w[3]};
-  if constexpr (MODE == kBF16X2) *reinterpret_cast<u32x4*>(L.act_w_lo + off) = u32x4{w[4], w[5], w[6], w[7]};
+  if constexpr (AM == kBF16X2) *reinterpret_cast<u32x4*>(L.act_w_lo + off) = u32x4{w[4], w[5], w[6], w[7]};
 }
 
-template <int W, int MODE, int I, int GP, int NT>
+template <int W, int MODE, int I, int GP, int NT, int AM = fwd_arith<MODE>()>
 __device__ __forceinline__ void act_store8(const Lane<W, MODE>& L, const float v[8]) {
   uint32_t w[8];
-  act_pack8<MODE>(v, w);
-  act_write8<W, MODE, I, GP, NT>(L, w);
+  act_pack8<AM>(v, w);
+  act_write8<W, MODE, I, GP, NT, AM>(L, w);
 }
 
 // Either layout: rows of groups g = 2 GP, 2 GP + 1 (see act_store8).
-template <int W, int MODE, int I, int GP, int NT>
+template <int W, int MODE, int I, int GP, int NT, int AM = fwd_arith<MODE>()>
 __device__ __forceinline__ void act_store_pair(const Lane<W, MODE>& L, const float v[8]) {
   if constexpr (MODE == kFP32) {
     act_store4_fp32<W, MODE, I, 2 * GP, NT>(L, v);
     act_store4_fp32<W, MODE, I, 2 * GP + 1, NT>(L, v + 4);
   } else {
-    act_store8<W, MODE, I, GP, NT>(L, v);
+    act_store8<W, MODE, I, GP, NT, AM>(L, v);
   }
 }
 
@@ -291,23 +326,24 @@ __device__ __forceinline__ void static_for(F&& f) {
 // (voff = p*stream_bytes + s*MT*1024 + lane*16) serves every matrix and step; the
 // step goes in the scalar offset and i*1024 in the instruction's immediate.
 // Software pipeline: A is loaded two K steps ahead, B (LDS) one step ahead.
+// AM is the K loop's arithmetic (fwd_arith / rev_arith of the tile's mode).
 // ----------------------------------------------------------------------------
-template <int MODE>
+template <int AM>
 struct BFrag {
   bf16x8 h[2], l[2];
   f32x4 f[2];
 };
 
-template <int W, int MODE>
-__device__ __forceinline__ void load_b(BFrag<MODE>& b, const char* br) {
-  if constexpr (MODE == kFP32) {
+template <int W, int MODE, int AM>
+__device__ __forceinline__ void load_b(BFrag<AM>& b, const char* br) {
+  if constexpr (AM == kFP32) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) b.f[nt] = *reinterpret_cast<const f32x4*>(br + nt * 1024);
   } else {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       b.h[nt] = *reinterpret_cast<const bf16x8*>(br + nt * 512);
-      if constexpr (MODE == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + Geo<W, MODE>::LO_OFF + nt * 512);
+      if constexpr (AM == kBF16X2) b.l[nt] = *reinterpret_cast<const bf16x8*>(br + Geo<W, MODE>::LO_OFF + nt * 512);
     }
   }
 }
@@ -325,25 +361,30 @@ __device__ __forceinline__ void load_a(f32x4 (&af)[(Geo<W, MODE>::MT)], __amdgpu
 // then at once the reload of a[i] for step `next` -- the fragment's registers
 // are free as soon as its last MFMA has issued.  The scheduling barriers keep
 // the compiler from sinking the loads to the end of the loop body.
-template <int W, int MODE>
+template <int W, int MODE, int AM>
 __device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], f32x4 (&af)[(Geo<W, MODE>::MT)],
-                                                const BFrag<MODE>& b, __amdgpu_buffer_rsrc_t rs, int voff,
+                                                const BFrag<AM>& b, __amdgpu_buffer_rsrc_t rs, int voff,
                                                 int next) {
   constexpr int MT = Geo<W, MODE>::MT;
   const int soff = next * Geo<W, MODE>::PMT * 1024;
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
-    if constexpr (MODE == kFP32) {
+    if constexpr (AM == kFP32) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
           acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], b.f[nt][q], acc[i][nt], 0, 0, 0);
+    } else if constexpr (AM == kF16) {
+      const f16x8 a8 = __builtin_bit_cast(f16x8, af[i]);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, __builtin_bit_cast(f16x8, b.h[nt]), acc[i][nt], 0, 0, 0);
     } else {
       const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.h[nt], acc[i][nt], 0, 0, 0);
-      if constexpr (MODE == kBF16X2) {
+      if constexpr (AM == kBF16X2) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
           acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.l[nt], acc[i][nt], 0, 0, 0);
@@ -360,25 +401,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* base) 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-template <int W, int MODE>
+template <int W, int MODE, int AM>
 __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs, int voff,
                                            const char* br) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even
   constexpr int SB = Geo<W, MODE>::STEP_BYTES;
   f32x4 a0[MT], a1[MT];
-  BFrag<MODE> b0, b1;
+  BFrag<AM> b0, b1;
   load_a<W, MODE>(a0, rs, voff, 0);
   load_a<W, MODE>(a1, rs, voff, 1);
-  load_b<W, MODE>(b0, br);
+  load_b<W, MODE, AM>(b0, br);
 #pragma unroll 1
   for (int s = 0; s < NS; s += 2) {
-    load_b<W, MODE>(b1, br + SB);  // B of step s+1, one step ahead
+    load_b<W, MODE, AM>(b1, br + SB);  // B of step s+1, one step ahead
     __builtin_amdgcn_sched_barrier(0);
-    mma_step_reload<W, MODE>(acc, a0, b0, rs, voff, s + 2 < NS ? s + 2 : NS - 1);
-    load_b<W, MODE>(b0, s + 2 < NS ? br + 2 * SB : br);  // B of step s+2
+    mma_step_reload<W, MODE, AM>(acc, a0, b0, rs, voff, s + 2 < NS ? s + 2 : NS - 1);
+    load_b<W, MODE, AM>(b0, s + 2 < NS ? br + 2 * SB : br);  // B of step s+2
     __builtin_amdgcn_sched_barrier(0);
-    mma_step_reload<W, MODE>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
+    mma_step_reload<W, MODE, AM>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
     br += 2 * SB;
   }
 }
@@ -490,15 +531,16 @@ constexpr bool defer_stores(bool last_forward) {
 // The packed words of elements 8 GP .. 8 GP + 7 of an accumulator go back into
 // those elements (consumed in order, so no extra registers), and are written out
 // after the barrier.
-template <int MODE, int GP>
+template <int AM, int GP>
 __device__ __forceinline__ void park_packed(const float v[8], f32x16& a) {
   uint32_t w[8];
-  act_pack8<MODE>(v, w);
+  act_pack8<AM>(v, w);
+  constexpr int NWORDS = AM == kBF16X2 ? 8 : 4;  // hi and lo words, or hi only
 #pragma unroll
-  for (int k = 0; k < 8; ++k) a[8 * GP + k] = __uint_as_float(w[k]);
+  for (int k = 0; k < NWORDS; ++k) a[8 * GP + k] = __uint_as_float(w[k]);
 }
 
-template <int W, int MODE>
+template <int W, int MODE, int AM>
 __device__ __forceinline__ void write_packed(const Lane<W, MODE>& ln, const f32x16 (&acc)[(Geo<W, MODE>::MT)][2]) {
   static_for<Geo<W, MODE>::MT>([&](auto I) {
     static_for<2>([&](auto GP) {
@@ -506,7 +548,7 @@ __device__ __forceinline__ void write_packed(const Lane<W, MODE>& ln, const f32x
         uint32_t w[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) w[k] = __float_as_uint(acc[I][NT][8 * GP + k]);
-        act_write8<W, MODE, I, GP, NT>(ln, w);
+        act_write8<W, MODE, I, GP, NT, AM>(ln, w);
       });
     });
   });
@@ -528,7 +570,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][nt][4 * g + r] = b4[r];
     }
-  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+  layer_gemm<W, MODE, fwd_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+  // arithmetic of what this layer stores: the next layer's activations, or g4
+  // for the reverse sweep
+  constexpr int SA = L == 2 ? rev_arith<MODE>() : fwd_arith<MODE>();
   // With two waves per SIMD the epilogue arithmetic runs before the barrier (the
   // results wait in registers), overlapping the K loops of waves still running;
   // only the stores into the tile they read wait for it.
@@ -558,7 +603,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         w5r[1] = *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP + 4);
       }
       static_for<2>([&](auto NT) {
-        const float seed = b.xin[NT * 32 * Geo<W, MODE>::XIN_FLOATS + 11];
+        const float seed = b.xin[NT * 32 * Geo<W, MODE>::XIN_FLOATS + 11] * rev_scale<MODE>();
         float v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -574,8 +619,8 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
           }
         }
         if (L < 2 || want_grad) {
-          if constexpr (DEFER) park_packed<MODE, GP>(v, acc[I][NT]);
-          else act_store_pair<W, MODE, I, GP, NT>(ln, v);
+          if constexpr (DEFER) park_packed<SA, GP>(v, acc[I][NT]);
+          else act_store_pair<W, MODE, I, GP, NT, SA>(ln, v);
         }
       });
       __builtin_amdgcn_sched_barrier(0);
@@ -589,7 +634,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   }
   if constexpr (DEFER) {
     __syncthreads();  // every wave has finished reading the tile
-    if (L < 2 || want_grad) write_packed<W, MODE>(ln, acc);
+    if (L < 2 || want_grad) write_packed<W, MODE, SA>(ln, acc);
   }
   __syncthreads();
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
@@ -608,7 +653,8 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
-  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+  constexpr int RA = rev_arith<MODE>();
+  layer_gemm<W, MODE, RA>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
   constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
   if constexpr (!DEFER) __syncthreads();
   static_for<MT>([&](auto I) {
@@ -620,15 +666,15 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
           const int j = 8 * GP + q;
           v[q] = acc[I][NT][j] * unpark(sp[L - 1][I][NT][j], acc[I][NT][j]);
         }
-        if constexpr (DEFER) park_packed<MODE, GP>(v, acc[I][NT]);
-        else act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        if constexpr (DEFER) park_packed<RA, GP>(v, acc[I][NT]);
+        else act_store_pair<W, MODE, I, GP, NT, RA>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
   });
   if constexpr (DEFER) {
     __syncthreads();  // every wave has finished reading the tile
-    write_packed<W, MODE>(ln, acc);
+    write_packed<W, MODE, RA>(ln, acc);
   }
   __syncthreads();
   if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.g(L), td.ldb, td.q0, td.nvalid);  // g3 or g2
@@ -648,7 +694,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
-  layer_gemm<W, MODE>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
+  layer_gemm<W, MODE, rev_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
   float g1keep[TRAIN ? MT : 1][2][16];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -942,6 +988,10 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       for (int w = 1; w < G::NW; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
       vals[c] = sum;
     }
+    if constexpr (rev_scale<MODE>() != 1.0f) {
+#pragma unroll
+      for (int c = 1; c < G::RED_VALS; ++c) vals[c] *= 1.0f / rev_scale<MODE>();
+    }
     const float dv = vals[0] + *net.b5p;
     const int64_t q = q0 + n;
     const bool valid = q < qlimit;
@@ -1018,7 +1068,7 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   if (ntiles <= 0) return hipSuccess;
   const int64_t slots = (int64_t)num_cu * OCC;
   const int grid = (int)(ntiles < slots ? ntiles : slots);
-  if constexpr (PAIRS && W == 256 && MODE != kBF16X2 && !SPH) {  // training: width 256, FP32 or BF16
+  if constexpr (PAIRS && W == 256 && (MODE == kFP32 || MODE == kBF16) && !SPH) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
       hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job, 1,
                          ntiles);
@@ -1049,6 +1099,7 @@ static hipError_t launch_w(const DevNet& net, const Job& job, bool pairs, bool w
   switch (net.mode) {
     case kFP32: return launch_m<W, kFP32, SPH>(net, job, pairs, want_grad, num_cu, s);
     case kBF16: return launch_m<W, kBF16, SPH>(net, job, pairs, want_grad, num_cu, s);
+    case kBF16X2F16: return launch_m<W, kBF16X2F16, SPH>(net, job, pairs, want_grad, num_cu, s);
     default: return launch_m<W, kBF16X2, SPH>(net, job, pairs, want_grad, num_cu, s);
   }
 }

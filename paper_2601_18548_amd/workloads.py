@@ -211,7 +211,7 @@ class QueryWorkload:
     K: int
     Np: int
     width: int
-    precision: str  # "fp32" | "bf16" | "bf16x2"
+    precision: str  # "fp32" | "bf16" | "bf16x2" | "bf16x2_f16"
     knots: np.ndarray
     points: np.ndarray
     weights: Weights
@@ -222,7 +222,8 @@ def workload(name: str, seed: int = 0) -> QueryWorkload:
 
     small   : 16 knots x 64 uniform points, width 256 (1,024 pairs)
     fp32    : 64 knots x 4,096 patch points, width 256, FP32 (262,144 pairs)
-    bf16    : 128 knots x 16,384 patch points, width 512, BF16 (2,097,152 pairs)
+    bf16    : 128 knots x 16,384 patch points, width 512, BF16 matrix cores (split
+              activations forward, FP16 reverse sweep) (2,097,152 pairs)
     sphere  : the bf16 shape with sphere obstacles (patch-cloud centres, radii
               U[0.05, 0.25] m) and the 10-input network [p', r, a]
     """
@@ -233,10 +234,10 @@ def workload(name: str, seed: int = 0) -> QueryWorkload:
         return QueryWorkload(name, 64, 4096, 256, "fp32", knots(64, seed + 1),
                              points_patches(4096, seed + 2), weights(256, seed + 3))
     if name == "bf16":
-        return QueryWorkload(name, 128, 16384, 512, "bf16x2", knots(128, seed + 1),
+        return QueryWorkload(name, 128, 16384, 512, "bf16x2_f16", knots(128, seed + 1),
                              points_patches(16384, seed + 2), weights(512, seed + 3))
     if name == "sphere":
-        return QueryWorkload(name, 128, 16384, 512, "bf16x2", knots(128, seed + 1),
+        return QueryWorkload(name, 128, 16384, 512, "bf16x2_f16", knots(128, seed + 1),
                              spheres(16384, seed + 2), weights(512, seed + 3, in_dim=IN_DIM_SPHERE))
     raise KeyError(name)
 

@@ -52,6 +52,22 @@ def test_create_rejects_bad_config_and_blob():
     assert lib.gcdf_create(ctypes.byref(_cfg(width=256)), buf2, len(wrong_width), ctypes.byref(h)) == g.EINVAL
 
 
+def test_create_rejects_weights_outside_fp16_for_the_fp16_reverse_mode():
+    """BF16X2_F16 holds the BF16-rounded hidden weights as FP16: a weight that
+    rounds past FP16's largest finite value (|w| >= 65408: BF16 65536) or is not
+    finite is rejected before any device work."""
+    lib = g.library()
+    w = wl.weights(256, 0)
+    h = ctypes.c_void_p()
+    for bad_value in (65408.0, -1e5, float("inf"), float("nan")):
+        w2 = wl.Weights(w.width, w.depth, [m.copy() for m in w.mats], [b.copy() for b in w.biases], w.in_dim)
+        w2.mats[2][17, 5] = bad_value
+        blob = w2.to_blob()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        assert lib.gcdf_create(ctypes.byref(_cfg(precision=g.BF16X2_F16)), buf, len(blob), ctypes.byref(h)) == g.EINVAL
+        assert b"W3" in lib.gcdf_last_error(None) and b"FP16" in lib.gcdf_last_error(None)
+
+
 def test_calls_on_null_context_fail_cleanly():
     lib = g.library()
     assert lib.gcdf_eval(None, None, 1, None, 1, None, None) == g.EINVAL

@@ -79,7 +79,7 @@ def test_partitions_with_empty_rows_and_capacity(gcdf, cons, weights):
     assert np.array_equal(b[:cap], want_idx[:cap]) and np.all(b[cap:] == -5)
 
 
-@pytest.mark.parametrize("precision,tol_d,tol_j", [("bf16x2", 1e-3, 1e-2), ("fp32", 5e-5, 5e-5)])
+@pytest.mark.parametrize("precision,tol_d,tol_j", [("bf16x2", 1e-3, 1e-2), ("bf16x2_f16", 1e-3, 1e-2), ("fp32", 5e-5, 5e-5)])
 def test_csr_query_matches_dense_and_oracle(gcdf, cons, weights, precision, tol_d, tol_j):
     N, M = 24, 4000
     k = wl.trajectory(N, 6)

@@ -159,7 +159,8 @@ def test_serving_disabled_rejects_submit(gcdf, weights):
         Req(16, 512, 50).submit(ctx)
 
 
-@pytest.mark.parametrize("width,precision", [(512, "bf16x2"), (512, "bf16"), (512, "fp32"), (256, "fp32")])
+@pytest.mark.parametrize("width,precision", [(512, "bf16x2"), (512, "bf16"), (512, "fp32"), (256, "fp32"),
+                                             (256, "bf16x2_f16"), (512, "bf16x2_f16")])
 def test_other_widths_and_precisions_match_one_shot(gcdf, width, precision):
     """Serving instantiations beyond the benchmark's (width 512 runs 8 waves in the
     BF16 modes, FP32 runs 4): bitwise equal to the one-shot query, including a

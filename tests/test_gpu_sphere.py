@@ -16,7 +16,7 @@ from paper_2601_18548_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16": (0.25, 0.25)}
+TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16x2_f16": (1e-3, 1e-2), "bf16": (0.25, 0.25)}
 GiB = 1 << 30
 
 
@@ -41,7 +41,7 @@ def rel_j_err(J, Jr):
     return np.linalg.norm(J - Jr, axis=1) / np.maximum(nr, 1e-3 * np.median(nr))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x2", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2", "bf16x2_f16", "bf16"])
 @pytest.mark.parametrize("width", [256, 512])
 def test_sphere_query_matches_oracle(gcdf, oracle_mod, precision, width):
     w = wl.weights(width, seed=41, in_dim=10)
@@ -62,7 +62,7 @@ def test_sphere_query_matches_oracle(gcdf, oracle_mod, precision, width):
         assert dd.max() <= tol_d and rj.max() <= tol_j
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2", "bf16x2_f16"])
 def test_zero_radius_column_equals_point_network_bitwise(gcdf, precision):
     """A sphere network whose radius column is zero and the point network
     without that column run the same arithmetic: equal bit for bit."""
