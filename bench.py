@@ -2,8 +2,9 @@
 """Throughput of the batched neural GCDF query on one MI355X.
 
 One step = one pass of the whole query over one batch: 128 knots x 16,384
-obstacle points (2,097,152 pairs), width-512 distance network, BF16 matrix
-cores with hi/lo split activations (FP32-class accuracy), producing the
+obstacle points (2,097,152 pairs), width-512 distance network on 16-bit matrix
+cores (forward: BF16 products of hi/lo split activations; reverse sweep: FP16
+products; FP32 accumulation; |dd| <= 1e-3, relative J error <= 1e-2), producing the
 distance d, the 9-dim configuration Jacobian J and the per-knot minimum
 (dmin, argmin) in one fused launch (gcdf_query).  Inputs are resident in HBM
 before the timed region.
@@ -366,7 +367,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bf16", choices=["bf16", "fp32", "small"])
     ap.add_argument("--precision", default=None, choices=sorted(PEAK_TFLOPS),
-                    help="precision of the timed query (default: the workload's)")
+                    help="precision of the timed query and the serving trace (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="skip the runs of the workload in the other precisions")
@@ -402,7 +403,8 @@ def main():
     g.library()  # fails loudly if the HIP library is missing
     if args.serve_sweep:
         for rate in [float(x) for x in args.serve_sweep.split(",")]:
-            print(json.dumps({"serving": serve_bench(g, torch, rate, args.serve_requests)}), flush=True)
+            print(json.dumps({"serving": serve_bench(g, torch, rate, args.serve_requests,
+                                                     precision=args.precision or "bf16x2_f16")}), flush=True)
         return
     wk = wl.workload(args.workload)
     if args.precision:
@@ -466,7 +468,7 @@ def main():
                                       "meets_1e-3": True}
         out["modes"] = modes
     if args.serve_requests > 0:
-        out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests)
+        out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests, precision=wk.precision)
         print("bench: serving p50 %.1f ms p99 %.1f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]),
               file=sys.stderr, flush=True)
     if not args.no_constraints and args.workload == "bf16":
