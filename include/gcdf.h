@@ -73,7 +73,8 @@ typedef enum {
     GCDF_BF16X2_F16 = 3 /* forward layers as BF16X2; the reverse sweep multiplies FP16 back-propagated
                          * values (scaled by 2^6) by the BF16-rounded transposed weights held as FP16:
                          * one product instead of two per reverse fragment, d as BF16X2, Jacobian
-                         * relative error ~1e-3.  Hidden weights must satisfy |w| < 65408; values
+                         * relative error a few 1e-3 (under 1e-2).  Hidden weights must satisfy
+                         * |w| < 65408; values
                          * back-propagated beyond ~1e3 in magnitude overflow FP16 */
 } gcdf_precision;
 

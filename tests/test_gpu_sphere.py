@@ -134,10 +134,11 @@ def test_sphere_bad_index_gives_nan_row(gcdf):
     assert cn[0] == dn[0, 0] and cn[3] == dn[1, 49]
 
 
-def test_sphere_serving_matches_one_shot_bitwise(gcdf):
+@pytest.mark.parametrize("precision", ["bf16x2", "bf16x2_f16"])
+def test_sphere_serving_matches_one_shot_bitwise(gcdf, precision):
     w = wl.weights(256, seed=46, in_dim=10)
-    srv = gcdf.Context(w.to_blob(), 256, "bf16x2", serve_mem_budget=2 * GiB, serve_slots=8)
-    one = gcdf.Context(w.to_blob(), 256, "bf16x2")
+    srv = gcdf.Context(w.to_blob(), 256, precision, serve_mem_budget=2 * GiB, serve_slots=8)
+    one = gcdf.Context(w.to_blob(), 256, precision)
     reqs = []
     for i, (K, Np) in enumerate([(20, 1000), (7, 333), (40, 2100)]):
         k, s = cu(wl.knots(K, 60 + i)), cu(wl.spheres(Np, 70 + i))
