@@ -198,3 +198,32 @@ def test_fp16_reverse_mode_ragged_and_value_only(gcdf, oracle_mod, width):
         dr, Jr = oracle_mod.eval_grad(w.to_blob(), k, p)
         assert np.abs(d - dr).max() <= 1e-3 and rel_j_err(J, Jr).max() <= 1e-2
         assert np.array_equal(ctx.eval(kt, pt).cpu().numpy(), d)
+
+
+def test_outputs_past_32_bit_offsets(gcdf, oracle_mod):
+    """1,024 knots x 262,143 points (the last tile of every row ragged), width 256,
+    the benchmark precision: J holds 2.4e9 floats (9.7 GB), so element offsets pass
+    2^31 and byte offsets 2^32.  Sampled pairs, the whole tail of the last row and
+    the per-knot minimum are checked; the samples are gathered on the device."""
+    K, Np = 1024, 262143
+    w = wl.weights(256, seed=13)
+    k = wl.knots(K, 21)
+    p = wl.points_patches(Np, 22)
+    print("case 32-bit offsets: K=%d Np=%d (J %.1f GB)" % (K, Np, K * Np * 36 / 1e9), flush=True)
+    ctx = gcdf.Context(w.to_blob(), 256, "bf16x2_f16")
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    d, J = ctx.eval_grad(kt, pt)
+    r = np.random.default_rng(1)
+    ki = np.concatenate([r.integers(0, K, 400), np.full(70, K - 1), [0, K // 2]])
+    pi = np.concatenate([r.integers(0, Np, 400), np.arange(Np - 70, Np), [0, Np - 1]])
+    kd, pd = torch.from_numpy(ki).cuda(), torch.from_numpy(pi).cuda()
+    ds, Js = d[kd, pd].cpu().numpy(), J[kd, pd].cpu().numpy()
+    dr, Jr = oracle_mod.eval_pairs(w.to_blob(), k, p, ki, pi)
+    dd, rj = np.abs(ds - dr), rel_j_err(Js, Jr)
+    report("32-bit offsets sampled", dd, rj)
+    assert dd.max() <= 1e-3 and rj.max() <= 1e-2
+    dmin, am = ctx.knot_min(kt, pt)
+    assert torch.equal(dmin, d.min(dim=1).values)
+    assert torch.equal(d[torch.arange(K, device="cuda"), am.long()], dmin)
+    del J, d
+    torch.cuda.empty_cache()
