@@ -430,7 +430,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16x2_f16": "bf16x2 fwd / f16 rev", "bf16x2": "bf16x2"}.get(wk.precision, wk.precision),
+        # forward products BF16 (hi/lo split), reverse-sweep products FP16, FP32 accumulation
+        "dtype": {"bf16x2_f16": "bf16x2/f16"}.get(wk.precision, wk.precision),
         "data": "synthetic (seeded knots, patch point clouds, He-normal random weights)",
         "config": {
             "workload": "%d knots x %d points, distance MLP 9->%dx4->1 SiLU, %s" %
