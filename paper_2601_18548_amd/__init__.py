@@ -138,7 +138,11 @@ def _need(t, shape, name):
 
 
 class Context:
-    """A libgcdf context: one network on one device."""
+    """A libgcdf context: one network on one device.
+
+    precision: "fp32", "bf16" (fast, misses the 1e-3 bar), "bf16x2" (split BF16
+    products, FP32-class error) or "bf16x2_f16" (split BF16 forward products, FP16
+    reverse-sweep products: d as bf16x2, Jacobian relative error a few 1e-3)."""
 
     def __init__(self, weight_blob: bytes, width: int, precision="bf16x2", device: int = 0, depth: int = 4,
                  max_knots: int = 0, serve_mem_budget: int = 0, serve_slots: int = 0):
