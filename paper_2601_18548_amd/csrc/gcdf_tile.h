@@ -360,13 +360,16 @@ __device__ __forceinline__ void load_a(f32x4 (&af)[(Geo<W, MODE>::MT)], __amdgpu
 // the two column blocks, so accumulations into one tile are two MFMAs apart),
 // then at once the reload of a[i] for step `next` -- the fragment's registers
 // are free as soon as its last MFMA has issued.  The scheduling barriers keep
-// the compiler from sinking the loads to the end of the loop body.
-template <int W, int MODE, int AM>
+// the compiler from sinking the loads to the end of the loop body.  ZC: the
+// accumulators start at zero, so the first product of each tile reads a zero C
+// operand instead of registers cleared beforehand.
+template <int W, int MODE, int AM, bool ZC = false>
 __device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], f32x4 (&af)[(Geo<W, MODE>::MT)],
                                                 const BFrag<AM>& b, __amdgpu_buffer_rsrc_t rs, int voff,
                                                 int next) {
   constexpr int MT = Geo<W, MODE>::MT;
   const int soff = next * Geo<W, MODE>::PMT * 1024;
+  const f32x16 zero = {};
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
     if constexpr (AM == kFP32) {
@@ -374,16 +377,19 @@ __device__ __forceinline__ void mma_step_reload(f32x16 (&acc)[(Geo<W, MODE>::MT)
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], b.f[nt][q], acc[i][nt], 0, 0, 0);
+          acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], b.f[nt][q], (ZC && q == 0) ? zero : acc[i][nt],
+                                                            0, 0, 0);
     } else if constexpr (AM == kF16) {
       const f16x8 a8 = __builtin_bit_cast(f16x8, af[i]);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt)
-        acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, __builtin_bit_cast(f16x8, b.h[nt]), acc[i][nt], 0, 0, 0);
+        acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, __builtin_bit_cast(f16x8, b.h[nt]),
+                                                            ZC ? zero : acc[i][nt], 0, 0, 0);
     } else {
       const bf16x8 a8 = __builtin_bit_cast(bf16x8, af[i]);
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.h[nt], acc[i][nt], 0, 0, 0);
+      for (int nt = 0; nt < 2; ++nt)
+        acc[i][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b.h[nt], ZC ? zero : acc[i][nt], 0, 0, 0);
       if constexpr (AM == kBF16X2) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
@@ -401,19 +407,31 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* base) 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-template <int W, int MODE, int AM>
+// ZERO: acc starts at zero (its contents on entry are not read).
+template <int W, int MODE, int AM, bool ZERO = false>
 __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs, int voff,
                                            const char* br) {
   constexpr int MT = Geo<W, MODE>::MT;
-  constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even
+  constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even, >= 16
   constexpr int SB = Geo<W, MODE>::STEP_BYTES;
   f32x4 a0[MT], a1[MT];
   BFrag<AM> b0, b1;
   load_a<W, MODE>(a0, rs, voff, 0);
   load_a<W, MODE>(a1, rs, voff, 1);
   load_b<W, MODE, AM>(b0, br);
+  int s = 0;
+  if constexpr (ZERO) {  // steps 0 and 1, the first writing acc from a zero C operand
+    load_b<W, MODE, AM>(b1, br + SB);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_step_reload<W, MODE, AM, true>(acc, a0, b0, rs, voff, 2);
+    load_b<W, MODE, AM>(b0, br + 2 * SB);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_step_reload<W, MODE, AM>(acc, a1, b1, rs, voff, 3);
+    br += 2 * SB;
+    s = 2;
+  }
 #pragma unroll 1
-  for (int s = 0; s < NS; s += 2) {
+  for (; s < NS; s += 2) {
     load_b<W, MODE, AM>(b1, br + SB);  // B of step s+1, one step ahead
     __builtin_amdgcn_sched_barrier(0);
     mma_step_reload<W, MODE, AM>(acc, a0, b0, rs, voff, s + 2 < NS ? s + 2 : NS - 1);
@@ -422,6 +440,23 @@ __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2],
     mma_step_reload<W, MODE, AM>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
     br += 2 * SB;
   }
+}
+
+// The reverse layers' accumulators start at zero: in single FP16 the first
+// products read a zero C operand (no clearing moves); the split forms clear the
+// registers first (the peeled first steps cost them spilled registers at W=512).
+template <int MODE>
+constexpr bool rev_zero_c() {
+  return rev_arith<MODE>() == kF16;
+}
+template <int W, int MODE>
+__device__ __forceinline__ void zero_acc(f32x16 (&acc)[(Geo<W, MODE>::MT)][2]) {
+#pragma unroll
+  for (int i = 0; i < Geo<W, MODE>::MT; ++i)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
 }
 
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -647,14 +682,9 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
                                            const float (&sp)[2][(Geo<W, MODE>::MT)][2][16], const TileDump& td) {
   constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
   constexpr int RA = rev_arith<MODE>();
-  layer_gemm<W, MODE, RA>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
+  if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
+  layer_gemm<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
   constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
   if constexpr (!DEFER) __syncthreads();
   static_for<MT>([&](auto I) {
@@ -688,13 +718,8 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   f32x16 acc[MT][2];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[i][nt][j] = 0.f;
-  layer_gemm<W, MODE, rev_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
+  if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
+  layer_gemm<W, MODE, rev_arith<MODE>(), rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
   float g1keep[TRAIN ? MT : 1][2][16];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
