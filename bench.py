@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the query shards by knots or points "
+        print("bench.py: measures one GPU only (the query shards by knots or points "
               "with no exchange but a K-value min all-reduce); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
