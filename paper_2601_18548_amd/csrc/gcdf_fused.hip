@@ -400,9 +400,11 @@ size_t packed_matrix_bytes(int width, int mode) {
 
 // Output element -> source element.  Chunk order: [wave][kstep][i] with 64 lanes per chunk.
 // Elements are rounded to BF16; with to_f16 the BF16 value is then stored as FP16
-// (exact for magnitudes in [2^-17, 65504], the range gcdf_create admits).
+// (exact for magnitudes in [2^-17, 65504], the range gcdf_create admits).  Element e
+// of lane (m, kh) in K step kb is column 16 kb + 8 kh + e, or with lane_order
+// 16 kb + 8 (e / 4) + 4 kh + e % 4 (the order the split modes keep activations in).
 __global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int W, int transpose,
-                                 int to_f16) {
+                                 int to_f16, int lane_order) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)W * W) return;
   const int MT = W / (32 * kWaves), NKB = W / 16;
@@ -413,7 +415,7 @@ __global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __rest
   const int kb = chunk % NKB; chunk /= NKB;
   const int wave = (int)chunk;
   const int row = 32 * (wave * MT + i) + (lane & 31);
-  const int col = 16 * kb + 8 * (lane >> 5) + e;
+  const int col = lane_order ? 16 * kb + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3) : 16 * kb + 8 * (lane >> 5) + e;
   const float v = transpose ? src[(int64_t)col * W + row] : src[(int64_t)row * W + col];
   const __bf16 vb = (__bf16)v;
   dst[idx] = to_f16 ? __builtin_bit_cast(uint16_t, (_Float16)(float)vb) : __builtin_bit_cast(uint16_t, vb);
@@ -443,7 +445,8 @@ hipError_t pack_matrix(const float* src, void* dst, int width, int mode, bool tr
                        transpose ? 1 : 0);
   else  // the reverse sweep of kBF16X2F16 multiplies the transposed matrix in FP16
     hipLaunchKernelGGL(pack_bf16_kernel, dim3(blocks), dim3(threads), 0, s, src, static_cast<uint16_t*>(dst), width,
-                       transpose ? 1 : 0, (transpose && mode == kBF16X2F16) ? 1 : 0);
+                       transpose ? 1 : 0, (transpose && mode == kBF16X2F16) ? 1 : 0,
+                       (mode == kBF16X2 || mode == kBF16X2F16) ? 1 : 0);
   return hipGetLastError();
 }
 

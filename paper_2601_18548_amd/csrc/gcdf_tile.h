@@ -145,6 +145,13 @@ constexpr float rev_scale() {
   return MODE == kBF16X2F16 ? 64.0f : 1.0f;
 }
 
+// The split modes order each K step's elements as the accumulators hold them (see
+// the activation tile below), so no lanes are exchanged before the LDS stores.
+template <int MODE>
+constexpr bool lane_k_order() {
+  return MODE == kBF16X2 || MODE == kBF16X2F16;
+}
+
 template <int W, int MODE>
 struct Geo {
   static constexpr int NW = waves_for<W, MODE>();    // waves per workgroup
@@ -177,11 +184,15 @@ struct Geo {
 // Activation tile in LDS (64 query columns).
 //  bf16 modes: K step s (rows 16s .. 16s+15) occupies STEP_BYTES at s*STEP_BYTES:
 //    its hi half, then (BF16X2) its lo half at +LO_OFF, so one base register with
-//    small immediate offsets reaches both.  Element (k, n) of a half sits in the
-//    16-byte group ((k%16)/8, n) at byte ((k%16)/8)*1024 + n*16, position k%8
-//    inside it.  The B fragment of step s, column block nt is the 2 KiB half, lane
-//    (n0, kh) reading the 16 bytes at kh*1024 + nt*512 + n0*16: every lane reads
-//    its own consecutive 16 bytes (no bank conflicts).
+//    small immediate offsets reaches both.  A half holds 16-byte groups (kh, n) at
+//    byte kh*1024 + n*16.  Pure BF16: group (kh, n) holds rows 16s + 8kh + j at
+//    position j.  The split modes (lane_k_order) hold rows 16s + 8(j/4) + 4kh + j%4
+//    at position j instead, which is the set of rows lane (n, kh) has in its
+//    accumulators, so their epilogues store without exchanging lanes; the packed
+//    weights order their K elements the same way (the sum over K is unchanged).
+//    The B fragment of step s, column block nt is the 2 KiB half, lane (n0, kh)
+//    reading the 16 bytes at kh*1024 + nt*512 + n0*16: every lane reads its own
+//    consecutive 16 bytes (no bank conflicts).
 //  fp32 mode : element (k, n) at (((k/8)*64 + n)*2 + k%2)*4 + (k%8)/2 floats; the
 //    B fragment of step s, block nt starts at s*2048 + nt*1024, lane (n0, kh) at
 //    +n0*32 + kh*16.
@@ -244,14 +255,22 @@ __device__ __forceinline__ void pack4(const float v[4], uint32_t& d0, uint32_t& 
 
 // bf16 modes: write rows of the group pair g = 2 GP, 2 GP + 1 (v[0..3] for g = 2 GP,
 // v[4..7] for g = 2 GP + 1) of column n = 32 nt + n0.  Lane (n0, h) holds k%8 in
-// [4h, 4h+4) of both 8-groups kh = 0 (g even) and kh = 1 (g odd); one swap across
-// the lane halves gives lane (n0, kh) the whole 8-group kh, written as 16 bytes.
+// [4h, 4h+4) of both 8-groups kh = 0 (g even) and kh = 1 (g odd).  SWAP (pure
+// BF16): one swap across the lane halves gives lane (n0, kh) the whole 8-group kh,
+// written as 16 bytes; otherwise (lane_k_order) the lane writes its own 8 values.
 // act_pack8 forms the 16-byte words (w[0..3] for the hi plane, w[4..7] for the lo
 // plane) and act_write8 stores them, so a caller can do the arithmetic before a
 // barrier and the stores after it.  AM: the arithmetic (fwd_arith / rev_arith).
-template <int AM>
+template <int AM, bool SWAP>
 __device__ __forceinline__ void act_pack8(const float v[8], uint32_t (&w)[8]) {
   auto put = [&](const uint32_t e0, const uint32_t e1, const uint32_t o0, const uint32_t o1, uint32_t* out) {
+    if constexpr (!SWAP) {
+      out[0] = e0;
+      out[1] = e1;
+      out[2] = o0;
+      out[3] = o1;
+      return;
+    }
     // e: g even (kh 0), o: g odd (kh 1).  Lanes 32..63 of the first operand trade
     // with lanes 0..31 of the second: afterwards lane (n0, kh) has k%8 in [0, 4)
     // in the first and [4, 8) in the second
@@ -293,7 +312,7 @@ __device__ __forceinline__ void act_write8(const Lane<W, MODE>& L, const uint32_
 template <int W, int MODE, int I, int GP, int NT, int AM = fwd_arith<MODE>()>
 __device__ __forceinline__ void act_store8(const Lane<W, MODE>& L, const float v[8]) {
   uint32_t w[8];
-  act_pack8<AM>(v, w);
+  act_pack8<AM, !lane_k_order<MODE>()>(v, w);
   act_write8<W, MODE, I, GP, NT, AM>(L, w);
 }
 
@@ -566,10 +585,10 @@ constexpr bool defer_stores(bool last_forward) {
 // The packed words of elements 8 GP .. 8 GP + 7 of an accumulator go back into
 // those elements (consumed in order, so no extra registers), and are written out
 // after the barrier.
-template <int AM, int GP>
+template <int MODE, int AM, int GP>
 __device__ __forceinline__ void park_packed(const float v[8], f32x16& a) {
   uint32_t w[8];
-  act_pack8<AM>(v, w);
+  act_pack8<AM, !lane_k_order<MODE>()>(v, w);
   constexpr int NWORDS = AM == kBF16X2 ? 8 : 4;  // hi and lo words, or hi only
 #pragma unroll
   for (int k = 0; k < NWORDS; ++k) a[8 * GP + k] = __uint_as_float(w[k]);
@@ -654,7 +673,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
           }
         }
         if (L < 2 || want_grad) {
-          if constexpr (DEFER) park_packed<SA, GP>(v, acc[I][NT]);
+          if constexpr (DEFER) park_packed<MODE, SA, GP>(v, acc[I][NT]);
           else act_store_pair<W, MODE, I, GP, NT, SA>(ln, v);
         }
       });
@@ -696,7 +715,7 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
           const int j = 8 * GP + q;
           v[q] = acc[I][NT][j] * unpark(sp[L - 1][I][NT][j], acc[I][NT][j]);
         }
-        if constexpr (DEFER) park_packed<RA, GP>(v, acc[I][NT]);
+        if constexpr (DEFER) park_packed<MODE, RA, GP>(v, acc[I][NT]);
         else act_store_pair<W, MODE, I, GP, NT, RA>(ln, v);
       });
       __builtin_amdgcn_sched_barrier(0);
