@@ -78,8 +78,9 @@ def measured_traffic(launch_pairs: int, precision: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def time_mode(g, torch, wk, precision, steps, warmup):
-    """Returns (seconds per step for gcdf_query, mean fused-kernel ms from events)."""
+def time_mode(g, torch, wk, precision, steps, warmup, keep_outputs=False):
+    """Returns (seconds per step for gcdf_query, mean fused-kernel ms from events),
+    plus the last launch's d and J (device tensors) with keep_outputs."""
     ctx = g.Context(wk.weights.to_blob(), wk.width, precision)
     kt = torch.from_numpy(wk.knots).cuda()
     pt = torch.from_numpy(wk.points).cuda()
@@ -105,7 +106,7 @@ def time_mode(g, torch, wk, precision, steps, warmup):
     torch.cuda.synchronize()
     kms = sum(a.elapsed_time(b) for a, b in evs) / steps
     ctx.close()
-    return dt, kms
+    return (dt, kms, d, J) if keep_outputs else (dt, kms)
 
 
 def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precision: str = "bf16x2_f16",
@@ -337,7 +338,10 @@ def table1_bench(g, torch, steps: int, warmup: int, batch: int = 65536, width: i
             "tflops_algorithmic": fl * steps / el / 1e12, "loss_first": first, "loss_last": float(losses[4])}
 
 
-def cpu_baseline(wk, seconds: float):
+def cpu_baseline(wk, seconds: float, torch=None, d_gpu=None, J_gpu=None):
+    """The FP64 oracle timed on a bounded random sample of the workload's pairs.
+    With the timed launch's outputs (d_gpu, J_gpu), also their errors against the
+    oracle on that sample: returns (baseline, accuracy or None)."""
     import numpy as np
 
     import oracle
@@ -350,14 +354,27 @@ def cpu_baseline(wk, seconds: float):
         ki = r.integers(0, wk.K, n)
         pi = r.integers(0, wk.Np, n)
         t0 = time.perf_counter()
-        oracle.eval_pairs(blob, wk.knots, wk.points, ki, pi, nthreads=threads)
+        dr, Jr = oracle.eval_pairs(blob, wk.knots, wk.points, ki, pi, nthreads=threads)
         el = time.perf_counter() - t0
         if el >= seconds * 0.5 or n >= 1 << 22:
             break
         n = int(n * min(16.0, max(2.0, seconds / max(el, 1e-3))))
     rate = n / el
-    return {"value": rate, "unit": "queries/s", "cores": oracle.threads(threads), "kind": "oracle",
+    base = {"value": rate, "unit": "queries/s", "cores": oracle.threads(threads), "kind": "oracle",
             "sample": "%d random (knot, point) pairs of the same workload, value + Jacobian in FP64, %.1f s" % (n, el)}
+    if d_gpu is None:
+        return base, None
+    kd, pd = torch.from_numpy(ki).to(d_gpu.device), torch.from_numpy(pi).to(d_gpu.device)
+    d = d_gpu[kd, pd].cpu().numpy().astype(np.float64)
+    J = J_gpu[kd, pd].cpu().numpy().astype(np.float64).reshape(-1, 9)
+    Jr = np.asarray(Jr).reshape(-1, 9)
+    dd = np.abs(d - np.asarray(dr))
+    nr = np.linalg.norm(Jr, axis=1)
+    rel = np.linalg.norm(J - Jr, axis=1) / np.maximum(nr, 1e-3 * np.median(nr))
+    acc = {"vs": "FP64 oracle", "pairs": int(n), "max_abs_dd": float(dd.max()), "mean_abs_dd": float(dd.mean()),
+           "max_rel_J": float(rel.max()), "p99_rel_J": float(np.percentile(rel, 99)), "mean_rel_J": float(rel.mean()),
+           "rel_J": "|J - J_ref| / max(|J_ref|, 1e-3 median |J_ref|) per pair"}
+    return base, acc
 
 
 def main():
@@ -412,7 +429,7 @@ def main():
     pairs = wk.K * wk.Np
     print("bench: workload %s (%d knots x %d points, width %d, %s), %d steps after %d warmup" %
           (args.workload, wk.K, wk.Np, wk.width, wk.precision, args.steps, args.warmup), file=sys.stderr, flush=True)
-    step_s, kernel_ms = time_mode(g, torch, wk, wk.precision, args.steps, args.warmup)
+    step_s, kernel_ms, d_out, J_out = time_mode(g, torch, wk, wk.precision, args.steps, args.warmup, keep_outputs=True)
     value = pairs / step_s
     fl = flops_per_pair(wk.width) * pairs
     achieved = fl / (kernel_ms * 1e-3) / 1e12
@@ -486,7 +503,9 @@ def main():
         print("bench: Table I training %.3f ms/step" % out["training_table1"]["ms_per_step"], file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wk, args.cpu_seconds)
+        # the oracle's sample doubles as an accuracy check of the timed launch's outputs
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(wk, args.cpu_seconds, torch, d_out, J_out)
+        print("bench: accuracy %s" % json.dumps(out["accuracy"]), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
