@@ -360,8 +360,20 @@ def cpu_baseline(wk, seconds: float, torch=None, d_gpu=None, J_gpu=None):
             break
         n = int(n * min(16.0, max(2.0, seconds / max(el, 1e-3))))
     rate = n / el
+    # the same oracle on one core, on the first pairs of the sample (~1/8 of the time)
+    n1 = max(64, min(n, int(rate * seconds / 8 / max(1, oracle.threads(threads)))))
+    t0 = time.perf_counter()
+    oracle.eval_pairs(blob, wk.knots, wk.points, ki[:n1], pi[:n1], nthreads=1)
+    rate1 = n1 / (time.perf_counter() - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     base = {"value": rate, "unit": "queries/s", "cores": oracle.threads(threads), "kind": "oracle",
-            "sample": "%d random (knot, point) pairs of the same workload, value + Jacobian in FP64, %.1f s" % (n, el)}
+            "sample": "%d random (knot, point) pairs of the same workload, value + Jacobian in FP64, %.1f s" % (n, el),
+            "value_1_core": rate1, "sample_1_core": "the first %d pairs of that sample" % n1, "cpu_model": model}
     if d_gpu is None:
         return base, None
     kd, pd = torch.from_numpy(ki).to(d_gpu.device), torch.from_numpy(pi).to(d_gpu.device)
