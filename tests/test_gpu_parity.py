@@ -227,3 +227,21 @@ def test_outputs_past_32_bit_offsets(gcdf, oracle_mod):
     assert torch.equal(d[torch.arange(K, device="cuda"), am.long()], dmin)
     del J, d
     torch.cuda.empty_cache()
+
+
+def test_fp16_reverse_sweep_with_large_back_propagated_values(gcdf, oracle_mod):
+    """BF16X2_F16 scales the reverse sweep by 2^6 into FP16 (largest finite 65504):
+    a network whose output weights are 100x larger back-propagates values up to ~35
+    (~2,200 after scaling), which must stay finite with the relative J error of the
+    unscaled network; d scales by 100, so its error bar does too."""
+    w = wl.weights(512, seed=3)
+    w.mats[4] = (w.mats[4] * 100.0).astype(np.float32)
+    k = wl.knots(8, 31)
+    p = wl.points_patches(700, 32)
+    print("case large reverse values: width 512 bf16x2_f16 K=8 Np=700", flush=True)
+    _, _, _, d, J = run_eval_grad(gcdf, w, "bf16x2_f16", k, p)
+    dr, Jr = oracle_mod.eval_grad(w.to_blob(), k, p)
+    assert np.all(np.isfinite(d)) and np.all(np.isfinite(J))
+    dd, rj = np.abs(d - dr), rel_j_err(J, Jr)
+    report("large reverse values", dd, rj)
+    assert dd.max() <= 100 * 1e-3 and rj.max() <= 1e-2
