@@ -702,10 +702,15 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
   constexpr int RA = rev_arith<MODE>();
+  // Single FP16 products use only the hi halves of the tile, so the two reverse
+  // layers alternate halves: g4 (hi) -> g3 (lo) -> g2 (hi).  Nobody reads the half
+  // a layer writes, so its stores need no barrier before them.
+  constexpr bool PP = RA == kF16 && !TRAIN;
+  const char* br = (PP && L == 1) ? ln.act_r + Geo<W, MODE>::LO_OFF : ln.act_r;
   if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
-  layer_gemm<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, ln.act_r);
-  constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
-  if constexpr (!DEFER) __syncthreads();
+  layer_gemm<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, br);
+  constexpr bool DEFER = !PP && defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
+  if constexpr (!DEFER && !PP) __syncthreads();
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
       static_for<2>([&](auto NT) {
@@ -715,8 +720,17 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
           const int j = 8 * GP + q;
           v[q] = acc[I][NT][j] * unpark(sp[L - 1][I][NT][j], acc[I][NT][j]);
         }
-        if constexpr (DEFER) park_packed<MODE, RA, GP>(v, acc[I][NT]);
-        else act_store_pair<W, MODE, I, GP, NT, RA>(ln, v);
+        if constexpr (PP) {
+          uint32_t w[8];
+          act_pack8<RA, !lane_k_order<MODE>()>(v, w);
+          typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+          constexpr int off = (2 * I + GP) * Geo<W, MODE>::STEP_BYTES + NT * 512;
+          *reinterpret_cast<u32x4*>((L == 2 ? ln.act_w_lo : ln.act_w) + off) = u32x4{w[0], w[1], w[2], w[3]};
+        } else if constexpr (DEFER) {
+          park_packed<MODE, RA, GP>(v, acc[I][NT]);
+        } else {
+          act_store_pair<W, MODE, I, GP, NT, RA>(ln, v);
+        }
       });
       __builtin_amdgcn_sched_barrier(0);
     });
