@@ -19,6 +19,9 @@ Prints one JSON line: pairs (queries) per second, plus
                  Jacobian pattern and the single-step projection (HBM roofline);
   training     : steps/s of the width-256 training step (batch 65,536, Adam);
   training_table1: the same with the paper's four-term Table I loss (FP32).
+The serving and training legs carry their own roofline objects (algorithmic
+TFLOP/s over wall time against the BF16, resp. FP32, dense peak); the FP32
+configuration (64 x 4,096, width 256) carries its own oracle timing and errors.
 """
 from __future__ import annotations
 
@@ -168,11 +171,17 @@ def serve_bench(g, torch, rate_hz: float, n_requests: int, seed: int = 7, precis
     lat = np.array([done_at[i] - trace[i].arrival_s for i in range(n_requests)]) * 1e3
     ctx.close()
     mean_pairs = float(np.mean([r.K * r.Np for r in trace]))
+    # algorithmic work of the completed queries over the whole trace (wall clock,
+    # arrival gaps and host admission included) against the dense BF16 peak
+    tf = pairs * flops_per_pair(256) / elapsed / 1e12
     return {"offered_req_per_s": rate_hz, "requests": n_requests, "precision": precision, "width": 256,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "completed_req_per_s": n_requests / elapsed,
             "queries_per_s": pairs / elapsed, "offered_queries_per_s": rate_hz * mean_pairs,
-            "overloaded": bool(n_requests / elapsed < 0.95 * rate_hz)}
+            "overloaded": bool(n_requests / elapsed < 0.95 * rate_hz),
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                         "frac": tf / PEAK_TFLOPS[precision],
+                         "work": "completed pairs x %d FLOP / trace wall time" % flops_per_pair(256)}}
 
 
 def _event_ms(torch, stream, fn, reps: int) -> float:
@@ -283,11 +292,15 @@ def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int =
         loss = train.mse_step(params, opt, tr, kt, pt, y)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    tr.close()
     # algorithmic work per sample: forward 6 W^2, reverse 6 W^2, weight gradients 6 W^2
     fl = 18 * width * width * batch
+    tf = fl * steps / el / 1e12
     return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "samples_per_s": batch * steps / el,
             "batch": batch, "width": width, "precision": "bf16 (FP32 master weights, FP32 accumulate)",
-            "tflops_algorithmic": fl * steps / el / 1e12,
+            "tflops_algorithmic": tf,
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                         "frac": tf / PEAK_TFLOPS["bf16"], "work": "18 W^2 FLOP per sample, whole step"},
             "loss_first": float(loss0.item()) if loss0 is not None else None, "loss_last": float(loss.item())}
 
 
@@ -330,12 +343,17 @@ def table1_bench(g, torch, steps: int, warmup: int, batch: int = 65536, width: i
         opt.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    tr.close()
     # algorithmic work per sample: 12 W x W products in the loss pass (forward, reverse,
     # tangent, adjoint) + 6 in the weight gradients + the query for J (6)
     fl = 24 * width * width * batch
+    tf = fl * steps / el / 1e12
     return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "batch": batch, "width": width,
             "precision": "fp32", "loss": "Table I, lambda = (5, 0.1, 0.01, 0.01), M = diag(4, 4, 1, ..., 1)",
-            "tflops_algorithmic": fl * steps / el / 1e12, "loss_first": first, "loss_last": float(losses[4])}
+            "tflops_algorithmic": tf,
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                         "frac": tf / PEAK_TFLOPS["fp32"], "work": "24 W^2 FLOP per sample, whole step"},
+            "loss_first": first, "loss_last": float(losses[4])}
 
 
 def cpu_baseline(wk, seconds: float, torch=None, d_gpu=None, J_gpu=None):
@@ -491,11 +509,19 @@ def main():
             print("bench: mode %s %.3f ms/step" % (prec, s * 1e3), file=sys.stderr, flush=True)
         # the FP32 configuration at its own shape: 64 knots x 4,096 points, width 256
         wk2 = wl.workload("fp32")
-        s2, kms2 = time_mode(g, torch, wk2, "fp32", 10, 2)
+        s2, kms2, d2, J2 = time_mode(g, torch, wk2, "fp32", 10, 2, keep_outputs=True)
         a2 = flops_per_pair(wk2.width) * wk2.K * wk2.Np / (kms2 * 1e-3) / 1e12
         modes["fp32_64x4096_w256"] = {"queries_per_s": wk2.K * wk2.Np / s2, "kernel_ms": kms2, "tflops": a2,
                                       "frac_of_peak": a2 / PEAK_TFLOPS["fp32"], "peak": PEAK_TFLOPS["fp32"],
                                       "meets_1e-3": True}
+        if not args.no_cpu_baseline:
+            # the oracle on this configuration's own pairs, and the launch's errors on them
+            b2, acc2 = cpu_baseline(wk2, args.cpu_seconds / 2, torch, d2, J2)
+            modes["fp32_64x4096_w256"]["cpu_baseline"] = b2
+            modes["fp32_64x4096_w256"]["accuracy"] = acc2
+            print("bench: fp32 64x4096 oracle %.0f queries/s (%d cores), accuracy %s" %
+                  (b2["value"], b2["cores"], json.dumps(acc2)), file=sys.stderr, flush=True)
+        del d2, J2
         out["modes"] = modes
     if args.serve_requests > 0:
         out["serving"] = serve_bench(g, torch, args.serve_rate, args.serve_requests, precision=wk.precision)
@@ -518,6 +544,8 @@ def main():
         # the oracle's sample doubles as an accuracy check of the timed launch's outputs
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(wk, args.cpu_seconds, torch, d_out, J_out)
         print("bench: accuracy %s" % json.dumps(out["accuracy"]), file=sys.stderr, flush=True)
+    del d_out, J_out
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

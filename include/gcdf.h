@@ -63,7 +63,8 @@ typedef enum {
     GCDF_EINVAL = 2,  /* bad argument (message says which) */
     GCDF_ENOMEM = 3,  /* device allocation failed, or a request can never fit the serving budget */
     GCDF_EDEVICE = 4, /* HIP runtime error */
-    GCDF_EBUSY = 5    /* serving queue full */
+    GCDF_EBUSY = 5,   /* serving queue full */
+    GCDF_ERANGE = 6   /* GCDF_BF16X2_F16: an earlier query's reverse sweep overflowed FP16 (see below) */
 } gcdf_status;
 
 typedef enum {
@@ -74,8 +75,15 @@ typedef enum {
                          * values (scaled by 2^6) by the BF16-rounded transposed weights held as FP16:
                          * one product instead of two per reverse fragment, d as BF16X2, Jacobian
                          * relative error a few 1e-3 (under 1e-2).  Hidden weights must satisfy
-                         * |w| < 65408; values
-                         * back-propagated beyond ~1e3 in magnitude overflow FP16 */
+                         * |w| < 65408; values back-propagated beyond ~1e3 in magnitude
+                         * overflow FP16.  A query whose d is finite but whose J is not
+                         * sets a flag of the context; the next query call (gcdf_eval,
+                         * gcdf_eval_grad, gcdf_knot_min, gcdf_query, gcdf_eval_grad_csr)
+                         * or gcdf_poll that sees it clears it and returns GCDF_ERANGE
+                         * without doing anything else (a poll's ticket stays valid).
+                         * The flag is written by the device: synchronise the stream of
+                         * the overflowing call before relying on the next call to
+                         * report it. */
 } gcdf_precision;
 
 typedef struct {
@@ -227,9 +235,11 @@ gcdf_status gcdf_project_csr(gcdf_ctx* ctx, const float* knots, int64_t N, const
 /* ------------------------------------------------------------------------ */
 
 /* One request: the pairs of K knots x Np points, with any subset of outputs
- * (NULL = not wanted; at least one must be given).  All pointers are device
- * memory owned by the caller and must stay valid until gcdf_poll returns
- * GCDF_OK (or an error) for the request's ticket. */
+ * (NULL = not wanted; at least one of d, J, dmin must be given).  All pointers
+ * are device memory owned by the caller and must stay valid until gcdf_poll
+ * returns GCDF_OK (or an error) for the request's ticket.  The outputs are
+ * bitwise equal to those of gcdf_query on the same inputs, whatever else the
+ * serving loop runs at the same time. */
 typedef struct {
     const float* knots;
     int64_t K;
@@ -239,6 +249,7 @@ typedef struct {
     float* J;        /* float32[K][Np][9] */
     float* dmin;     /* float32[K] */
     int32_t* argmin; /* int32[K]  (given together with dmin) */
+    float* Jmin;     /* float32[K][9]: J at (knot i, point argmin[i]); needs dmin/argmin */
 } gcdf_request;
 
 /* Queue a request and return at once with its ticket.  The serving loop
@@ -249,7 +260,8 @@ typedef struct {
  * the call (synchronise the streams that produce or initialise them), and the
  * buffers must not be touched again until gcdf_poll returns GCDF_OK.
  * ENOMEM: the request alone exceeds serve_mem_budget.  EBUSY: too many queued.
- * EINVAL: bad request or serving disabled (serve_mem_budget == 0). */
+ * EINVAL: bad request (NULL knots/points, K or Np <= 0, no output, only one of
+ * dmin/argmin, Jmin without them) or serving disabled (serve_mem_budget == 0). */
 gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket);
 
 /* GCDF_OK when the ticket's outputs are complete and visible to the caller's

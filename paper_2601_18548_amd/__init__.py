@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(HERE, "libgcdf.so")
 
 FP32, BF16, BF16X2, BF16X2_F16 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16x2": BF16X2, "bf16x2_f16": BF16X2_F16}
-OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, 1, 2, 3, 4, 5
-STATUS_NAMES = {0: "OK", 1: "PENDING", 2: "EINVAL", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUSY"}
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, EBUSY, ERANGE = 0, 1, 2, 3, 4, 5, 6
+STATUS_NAMES = {0: "OK", 1: "PENDING", 2: "EINVAL", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUSY", 6: "ERANGE"}
 
 
 class GcdfError(RuntimeError):
@@ -38,7 +38,7 @@ class _Config(ctypes.Structure):
 class _Request(ctypes.Structure):
     _fields_ = [("knots", ctypes.c_void_p), ("K", ctypes.c_int64), ("points", ctypes.c_void_p),
                 ("Np", ctypes.c_int64), ("d", ctypes.c_void_p), ("J", ctypes.c_void_p),
-                ("dmin", ctypes.c_void_p), ("argmin", ctypes.c_void_p)]
+                ("dmin", ctypes.c_void_p), ("argmin", ctypes.c_void_p), ("Jmin", ctypes.c_void_p)]
 
 
 _lib = None
@@ -130,11 +130,28 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _need(t, shape, name):
+def _need(t, shape, name, dtype=None, device=None):
+    """Raise unless t is a contiguous CUDA tensor of this shape and dtype (float32
+    by default), on `device` if given."""
     import torch
 
-    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
-        raise ValueError("%s must be a contiguous float32 CUDA tensor of shape %s" % (name, tuple(shape)))
+    dtype = torch.float32 if dtype is None else dtype
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must be a contiguous %s CUDA tensor of shape %s" % (name, dtype, tuple(shape)))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+
+
+def _need_min(K, dmin, argmin, Jmin, device):
+    """Shapes of the per-knot minimum outputs (None = not requested)."""
+    import torch
+
+    if dmin is not None:
+        _need(dmin, (K,), "dmin", device=device)
+    if argmin is not None:
+        _need(argmin, (K,), "argmin", torch.int32, device=device)
+    if Jmin is not None:
+        _need(Jmin, (K, 9), "Jmin", device=device)
 
 
 class Context:
@@ -161,11 +178,13 @@ class Context:
         # (spheres (x, y, z, r), (Np, 4)); the library has validated it
         self.in_dim = int.from_bytes(weight_blob[8:12], "little")
         self.obstacle_dim = self.in_dim - 6
+        self._live = {}  # serving ticket -> the request's tensors, until complete
 
     def close(self):
         if getattr(self, "_h", None):
-            library().gcdf_destroy(self._h)
+            library().gcdf_destroy(self._h)  # waits for every serving request
             self._h = None
+            self._live = {}
 
     def __del__(self):
         try:
@@ -226,10 +245,13 @@ class Context:
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
         _need(points, (Np, self.obstacle_dim), "points")
+        dev = knots.device
+        _need(points, (Np, self.obstacle_dim), "points", device=dev)
         if d is not None:
-            _need(d, (K, Np), "d")
+            _need(d, (K, Np), "d", device=dev)
         if J is not None:
-            _need(J, (K, Np, 9), "J")
+            _need(J, (K, Np, 9), "J", device=dev)
+        _need_min(K, dmin, argmin, Jmin, dev)
         _check(library().gcdf_query(self._h, _ptr(knots), K, _ptr(points), Np, _ptr(d), _ptr(J), _ptr(dmin),
                                     _ptr(argmin), _ptr(Jmin), _stream(stream)), self._h)
         return d, J, dmin, argmin, Jmin
@@ -312,25 +334,43 @@ class Context:
         return qz, eik
 
     # -- serving ------------------------------------------------------------
-    def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None) -> int:
+    def submit(self, knots, points, d=None, J=None, dmin=None, argmin=None, Jmin=None) -> int:
         """Queue a serving request.  The serving loop runs on the library's own
         stream, so the current torch stream (which may still be producing the
-        inputs or initialising the outputs) is synchronised first."""
+        inputs or initialising the outputs) is synchronised first.  The request's
+        tensors are kept alive here until poll() reports it complete."""
         import torch
 
-        if points.dim() != 2 or points.shape[1] != self.obstacle_dim:
-            raise ValueError("points must be (Np, %d)" % self.obstacle_dim)
-        torch.cuda.current_stream(knots.device).synchronize()
+        K, Np = knots.shape[0], points.shape[0]
+        dev = knots.device
+        _need(knots, (K, 9), "knots")
+        _need(points, (Np, self.obstacle_dim), "points", device=dev)
+        if d is not None:
+            _need(d, (K, Np), "d", device=dev)
+        if J is not None:
+            _need(J, (K, Np, 9), "J", device=dev)
+        _need_min(K, dmin, argmin, Jmin, dev)
+        torch.cuda.current_stream(dev).synchronize()
         req = _Request()
-        req.knots, req.K = knots.data_ptr(), knots.shape[0]
-        req.points, req.Np = points.data_ptr(), points.shape[0]
+        req.knots, req.K = knots.data_ptr(), K
+        req.points, req.Np = points.data_ptr(), Np
         req.d = d.data_ptr() if d is not None else None
         req.J = J.data_ptr() if J is not None else None
         req.dmin = dmin.data_ptr() if dmin is not None else None
         req.argmin = argmin.data_ptr() if argmin is not None else None
+        req.Jmin = Jmin.data_ptr() if Jmin is not None else None
         t = ctypes.c_uint64()
         _check(library().gcdf_submit(self._h, ctypes.byref(req), ctypes.byref(t)), self._h)
+        # the device writes through these pointers until the request completes
+        self._live[t.value] = (knots, points, d, J, dmin, argmin, Jmin)
         return t.value
 
     def poll(self, ticket: int) -> bool:
-        return _check(library().gcdf_poll(self._h, ticket), self._h) == OK
+        try:
+            done = _check(library().gcdf_poll(self._h, ticket), self._h) == OK
+        except GcdfError:
+            self._live.pop(ticket, None)
+            raise
+        if done:
+            self._live.pop(ticket, None)
+        return done

@@ -42,9 +42,8 @@ struct gcdf_ctx {
   gcdf::DevNet net{};
   void* wbuf = nullptr;               // all packed weights
   unsigned long long* minkey = nullptr;  // [max_knots]
-  int64_t* pair_k = nullptr;          // [max_knots]
-  int64_t* pair_p = nullptr;          // [max_knots]
   int64_t* tile_off = nullptr;        // [max_knots + 1] (CSR query)
+  uint32_t* overflow = nullptr;       // pinned host word written by the device (GCDF_BF16X2_F16)
   gcdf::Server* server = nullptr;
 };
 
@@ -64,8 +63,18 @@ struct DeviceGuard {
   }
 };
 
-gcdf_status check_query(const gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np) {
+// The sticky FP16-overflow flag of a GCDF_BF16X2_F16 context: reported (and
+// cleared) by the first query call or poll that sees it.
+gcdf_status take_overflow(gcdf_ctx* ctx) {
+  if (ctx->overflow && __atomic_exchange_n(ctx->overflow, 0u, __ATOMIC_ACQ_REL) != 0)
+    return fail(GCDF_ERANGE, "an earlier query's FP16 reverse sweep overflowed: its J holds Inf/NaN "
+                             "(back-propagated values beyond the FP16 range of the GCDF_BF16X2_F16 precision)");
+  return GCDF_OK;
+}
+
+gcdf_status check_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np) {
   if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
+  if (gcdf_status st = take_overflow(ctx); st != GCDF_OK) return st;
   if (!knots || !points) return fail(GCDF_EINVAL, "knots/points pointer is NULL");
   if (K <= 0 || Np <= 0) return fail(GCDF_EINVAL, "K and Np must be positive (K=%lld, Np=%lld)", (long long)K, (long long)Np);
   if (K > INT64_MAX / 9 / Np) return fail(GCDF_EINVAL, "K*Np*9 overflows int64");
@@ -146,7 +155,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   const size_t off_b5 = align(off_w5 + (size_t)W * 4);
   const size_t off_m = align(off_b5 + 4);
   const size_t total = off_m + 6 * align(mbytes);
-  const size_t ws = (size_t)c->cfg.max_knots * (8 + 8 + 8 + 8) + 8;
+  const size_t ws = (size_t)c->cfg.max_knots * (8 + 8) + 8;
   float* staging = nullptr;
   e = hipMalloc(&c->wbuf, total);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&c->minkey), ws);
@@ -156,9 +165,7 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
     gcdf_destroy(c);
     return fail(GCDF_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
-  c->pair_k = reinterpret_cast<int64_t*>(c->minkey + c->cfg.max_knots);
-  c->pair_p = c->pair_k + c->cfg.max_knots;
-  c->tile_off = c->pair_p + c->cfg.max_knots;
+  c->tile_off = reinterpret_cast<int64_t*>(c->minkey + c->cfg.max_knots);
   hipStream_t s = nullptr;
   e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMemcpyAsync(staging, static_cast<const char*>(blob) + kHeader, 4 * nfloat, hipMemcpyHostToDevice, s);
@@ -207,6 +214,16 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   c->net.bh = bh;
   c->net.w5 = w5;
   c->net.b5p = reinterpret_cast<const float*>(base + off_b5);
+  if (mode == GCDF_BF16X2_F16) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->overflow), sizeof(uint32_t), hipHostMallocCoherent);
+    if (e != hipSuccess) {
+      c->overflow = nullptr;
+      gcdf_destroy(c);
+      return fail(GCDF_ENOMEM, "pinned host allocation failed: %s", hipGetErrorString(e));
+    }
+    *c->overflow = 0;
+    c->net.overflow = c->overflow;
+  }
   if (cfg->serve_mem_budget > 0) {
     gcdf_status st = gcdf::server_start(c, cfg->serve_mem_budget, cfg->serve_slots > 0 ? cfg->serve_slots : 64, &c->server);
     if (st != GCDF_OK) {
@@ -226,6 +243,10 @@ void gcdf_destroy(gcdf_ctx* ctx) {
   if (ctx->server) gcdf::server_stop(ctx->server);
   hipFree(ctx->wbuf);
   hipFree(ctx->minkey);
+  if (ctx->overflow) {
+    (void)hipDeviceSynchronize();  // no kernel of this context may still write the word
+    hipHostFree(ctx->overflow);
+  }
   delete ctx;
 }
 
@@ -253,17 +274,15 @@ gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float
   job.J = J;
   job.minkey = want_min ? ctx->minkey : nullptr;
   if (e == hipSuccess) e = gcdf::launch_fused(ctx->net, job, false, J != nullptr, ctx->num_cu, s);
-  if (e == hipSuccess && want_min)
-    e = gcdf::launch_minkey_decode(ctx->minkey, K, dmin, argmin, Jmin ? ctx->pair_k : nullptr,
-                                   Jmin ? ctx->pair_p : nullptr, s);
+  if (e == hipSuccess && want_min) e = gcdf::launch_minkey_decode(ctx->minkey, K, dmin, argmin, s);
   if (e == hipSuccess && Jmin) {
+    // the K pairs (knot i, point argmin[i]) through the pair-list kernel
     gcdf::Job pj{};
     pj.knots = knots;
     pj.points = points;
     pj.K = K;
     pj.Np = Np;
-    pj.kidx = ctx->pair_k;
-    pj.pidx = ctx->pair_p;
+    pj.pidx32 = argmin;
     pj.npairs = K;
     pj.J = Jmin;
     e = gcdf::launch_fused(ctx->net, pj, true, true, ctx->num_cu, s);
@@ -414,6 +433,7 @@ gcdf_status gcdf_submit(gcdf_ctx* ctx, const gcdf_request* req, uint64_t* ticket
 gcdf_status gcdf_poll(gcdf_ctx* ctx, uint64_t ticket) {
   if (!ctx) return fail(GCDF_EINVAL, "ctx is NULL");
   if (!ctx->server) return fail(GCDF_EINVAL, "serving is disabled (serve_mem_budget == 0)");
+  if (gcdf_status st = take_overflow(ctx); st != GCDF_OK) return st;
   return gcdf::server_poll(ctx->server, ticket);
 }
 

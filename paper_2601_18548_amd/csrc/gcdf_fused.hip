@@ -510,7 +510,7 @@ hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t
 }
 
 __global__ void minkey_decode_kernel(const unsigned long long* __restrict__ key, int64_t K, float* dmin,
-                                     int32_t* argmin, int64_t* kidx, int64_t* pidx) {
+                                     int32_t* argmin) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   const unsigned long long k = key[i];
@@ -519,16 +519,13 @@ __global__ void minkey_decode_kernel(const unsigned long long* __restrict__ key,
   if (dmin) dmin[i] = __uint_as_float(u);
   // every knot of a launch receives at least one key; an untouched slot would
   // decode to index 0 rather than an out-of-range point
-  const int32_t j = (k == ~0ull) ? 0 : (int32_t)(uint32_t)(k & 0xffffffffu);
-  if (argmin) argmin[i] = j;
-  if (kidx) kidx[i] = i;
-  if (pidx) pidx[i] = j;
+  if (argmin) argmin[i] = (k == ~0ull) ? 0 : (int32_t)(uint32_t)(k & 0xffffffffu);
 }
 
 hipError_t launch_minkey_decode(const unsigned long long* minkey, int64_t K, float* dmin, int32_t* argmin,
-                                int64_t* kidx, int64_t* pidx, hipStream_t s) {
+                                hipStream_t s) {
   hipLaunchKernelGGL(minkey_decode_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, minkey, K, dmin,
-                     argmin, kidx, pidx);
+                     argmin);
   return hipGetLastError();
 }
 

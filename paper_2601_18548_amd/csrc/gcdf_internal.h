@@ -28,6 +28,9 @@ struct DevNet {
   const float* b5p;   // device pointer to the output bias
   const void* fwd[3]; // W2, W3, W4 as matrix-core A fragments (see pack_matrix)
   const void* bwd[3]; // W2^T, W3^T, W4^T, same layout
+  // kBF16X2F16: set to 1 (host-visible memory) by any query whose d is finite but
+  // whose J is not, i.e. the FP16 reverse sweep overflowed (nullable)
+  uint32_t* overflow;
 };
 
 // What one fused launch computes.
@@ -36,9 +39,11 @@ struct Job {
   const float* points;       // [Np][3]
   int64_t K, Np;
   // pair list (pairs mode): pair i = (knots[kidx[i]], points[pidx[i]]); NULL index arrays
-  // mean pair i = (knots[i], points[i]).
+  // mean pair i = (knots[i], points[i]).  pidx32, when set, replaces pidx (32-bit point
+  // indices, e.g. a per-knot argmin array: pair i = (knots[i], points[argmin[i]])).
   const int64_t* kidx;
   const int64_t* pidx;
+  const int32_t* pidx32;
   int64_t npairs;
   // CSR pairs (pairs mode, when csr_off is set): pair r belongs to the knot i with
   // csr_off[i] <= r < csr_off[i+1] (i < csr_n) and to point csr_idx[r]; a point index
@@ -119,10 +124,9 @@ hipError_t launch_fused_sphere(const DevNet& net, const Job& job, bool pairs, bo
 // minkey[i] = all ones, for i < K (fill kernel; graph-capture safe).
 hipError_t launch_minkey_init(unsigned long long* minkey, int64_t K, hipStream_t s);
 
-// Decode keys into dmin / argmin; if kidx/pidx given, also write the argmin
-// pair list (kidx[i] = i, pidx[i] = argmin[i]).
+// Decode keys into dmin / argmin.
 hipError_t launch_minkey_decode(const unsigned long long* minkey, int64_t K, float* dmin, int32_t* argmin,
-                                int64_t* kidx, int64_t* pidx, hipStream_t s);
+                                hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Serving: a persistent kernel claims tiles of published requests.
@@ -130,6 +134,11 @@ hipError_t launch_minkey_decode(const unsigned long long* minkey, int64_t K, flo
 constexpr int kMaxSlots = 256;
 
 // One request as the device sees it (written by the host before publication).
+// The host rewrites a slot's descriptor only after its previous request has
+// completed, seqlock-style: seq = kDescWriting, the fields, then seq = the new
+// request's number.  A reader that finds seq != the request it wants (before or
+// after reading a field) knows that request has completed.
+constexpr uint64_t kDescWriting = ~0ull;
 struct ServeDesc {
   uint64_t seq;         // request sequence number; slot = seq % slots
   const float* knots;
@@ -141,6 +150,7 @@ struct ServeDesc {
   unsigned long long* minkey;  // [K], all ones on entry; restored to all ones on completion
   float* dmin;
   int32_t* argmin;
+  float* Jmin;                 // [K][9] J at the argmin pairs (NULL: not wanted; needs dmin)
   int32_t want_grad;
   int32_t pad;
 };
@@ -150,6 +160,8 @@ struct ServeCtl {
   uint64_t published;              // number of requests published (host writes, release)
   uint32_t stop;                   // host: exit when no work is claimable
   uint32_t slots;                  // number of request slots in use (<= kMaxSlots)
+  uint32_t fault;                  // device: a protocol invariant failed (the host stops serving)
+  uint32_t pad;
   uint64_t complete[kMaxSlots];    // seq + 1 of the last request completed in each slot (device writes)
   ServeDesc desc[kMaxSlots];
 };

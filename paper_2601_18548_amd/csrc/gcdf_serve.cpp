@@ -1,6 +1,6 @@
 // Serving loop: continuous batching of gcdf_request on one device.
 //
-// Host side of the persistent serving kernel (serve_loop in gcdf_fused.hip):
+// Host side of the persistent serving kernel (serve_loop in gcdf_serve_kernel.hip):
 //  * gcdf_submit queues a request and returns its ticket at once;
 //  * a worker thread admits queued requests in FIFO order while a request slot
 //    is free and the in-flight memory stays within the budget, writes each
@@ -86,6 +86,7 @@ size_t request_bytes(const gcdf_request& r, int obstacle_floats) {
   if (r.d) b += pairs * 4;
   if (r.J) b += pairs * 36;
   if (r.dmin) b += (size_t)r.K * 16;  // dmin + argmin + key scratch
+  if (r.Jmin) b += (size_t)r.K * 36;
   return b;
 }
 
@@ -156,7 +157,10 @@ struct Server {
       const int64_t nblk = (t.req.Np + kTileQ - 1) / kTileQ;
       const int64_t ntiles = t.req.K * nblk;
       ServeDesc& d = ctl->desc[s];
-      d.seq = seq;
+      // seqlock: a device reader that sees the marker or another number knows the
+      // slot's previous request has completed (reap_locked freed the slot)
+      __atomic_store_n(&d.seq, kDescWriting, __ATOMIC_RELAXED);
+      std::atomic_thread_fence(std::memory_order_release);  // marker before the fields
       d.knots = t.req.knots;
       d.points = t.req.points;
       d.K = t.req.K;
@@ -170,7 +174,9 @@ struct Server {
       d.minkey = off >= 0 ? keys + off : nullptr;
       d.dmin = t.req.dmin;
       d.argmin = t.req.argmin;
+      d.Jmin = t.req.Jmin;
       d.want_grad = t.req.J ? 1 : 0;
+      __atomic_store_n(&d.seq, seq, __ATOMIC_RELEASE);  // fields before the number
       __atomic_store_n(&ctl->published, seq + 1, __ATOMIC_RELEASE);
       t.state = TState::kRunning;
       t.seq = seq;
@@ -208,6 +214,7 @@ struct Server {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     while (!quit) {
+      if (__atomic_load_n(&ctl->fault, __ATOMIC_ACQUIRE) != 0) device_error = GCDF_EDEVICE;
       reap_locked();
       admit_locked();
       if (device_error == GCDF_OK) ensure_kernel_locked();
@@ -285,6 +292,7 @@ gcdf_status server_submit(Server* sv, const gcdf_request* r, uint64_t* ticket) {
   if (r->K > INT64_MAX / 9 / r->Np) return set_error(GCDF_EINVAL, "request K*Np*9 overflows int64");
   if (!r->d && !r->J && !r->dmin) return set_error(GCDF_EINVAL, "request asks for no output");
   if ((r->dmin == nullptr) != (r->argmin == nullptr)) return set_error(GCDF_EINVAL, "dmin and argmin go together");
+  if (r->Jmin && !r->dmin) return set_error(GCDF_EINVAL, "Jmin needs dmin and argmin");
   if (r->dmin && r->Np > INT32_MAX) return set_error(GCDF_EINVAL, "request Np exceeds 2^31-1");
   if (r->K * ((r->Np + kTileQ - 1) / kTileQ) >= ((int64_t)1 << 32)) return set_error(GCDF_EINVAL, "request too large");
   const size_t bytes = request_bytes(*r, ctx_net(sv->ctx).in_dim == kInDimSphere ? 4 : 3);

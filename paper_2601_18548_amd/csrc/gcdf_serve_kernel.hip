@@ -8,7 +8,8 @@ namespace gcdf {
 // with its own cursor and claims tiles from the slot's (seq, count) word (a
 // compare-and-swap re-tags it for a new request, a fetch_add hands out the
 // rest), so a late workgroup can never run tiles of a request that has since
-// been replaced in its slot under the wrong descriptor.  The first workgroup
+// been replaced in its slot under the wrong descriptor (descriptors are read
+// seqlock-style, see desc_ntiles).  The first workgroup
 // that stays idle ends the launch for all (the drain word); tiles not yet
 // claimed then wait in the claim words for the next launch.
 //
@@ -25,6 +26,19 @@ namespace gcdf {
 template <class T>
 __device__ __forceinline__ T sys_relaxed(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Tile count of request `want` from its slot's descriptor, read seqlock-style:
+// the descriptor's seq before and after the read must both be `want`.  Returns
+// false if the slot no longer holds `want` (it has completed and the host is
+// rewriting or has rewritten the slot for a later request).
+__device__ __forceinline__ bool desc_ntiles(const ServeDesc* d, uint64_t want, int64_t& nt) {
+  const uint64_t a = sys_relaxed(&d->seq);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // system scope: the field read follows
+  nt = sys_relaxed(&d->ntiles);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the field read precedes the re-check
+  const uint64_t b = sys_relaxed(&d->seq);
+  return a == want && b == want;
 }
 
 template <int W, int MODE, bool SPH>
@@ -81,7 +95,16 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
         if (seq < pub) {
           const uint32_t s = (uint32_t)(seq % slots);
           if (nt_seq != seq) {
-            ntiles = sys_relaxed(&ctl->desc[s].ntiles);
+            // A cursor behind the others can reach a request that has completed and
+            // whose slot the host has already given to a later request: the
+            // descriptor then describes that later request, and its tile count must
+            // not be taken for seq's.
+            if (!desc_ntiles(&ctl->desc[s], seq, ntiles)) {
+              if (open_count && cur_seq == seq) report();  // (none: seq is complete)
+              ++seq;
+              if (fin_seq >= 0) break;
+              continue;
+            }
             nt_seq = seq;
           }
           // Claim word of the slot: (request tag << 32) | tiles handed out.  The first
@@ -115,18 +138,38 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
             // took the slot: the add handed out tile wc of that request, which must be
             // run here.  Its tag is the low half of its sequence number.
             const uint64_t later = seq + ((ws - s32) & 0xffffffffull);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // its descriptor
-            const int64_t lnt = sys_relaxed(&ctl->desc[s].ntiles);
             // (no tiles of seq can be unreported here: seq could not have completed)
             seq = later;
             if (pub < later + 1) pub = later + 1;
-            nt_seq = later;
-            ntiles = lnt;
-            if ((int64_t)wc < lnt) { got_seq = (int64_t)later; got_tile = (int64_t)wc; }
+            int64_t lnt = 0;
+            bool held = false;
+            // The request that tagged the word was published before its first claim,
+            // so its descriptor is in place; a read that misses it is a visibility
+            // delay, re-read (bounded).  A slot holding a newer request means `later`
+            // has completed, so all its tiles were handed out: wc is past them.
+            for (int tries = 0; tries < (1 << 20); ++tries) {
+              const uint64_t ds = sys_relaxed(&ctl->desc[s].seq);
+              if (ds != kDescWriting && ds < later) {
+                __builtin_amdgcn_s_sleep(2);
+                continue;
+              }
+              held = desc_ntiles(&ctl->desc[s], later, lnt);
+              if (held || ds != later) break;
+            }
+            if (!held && sys_relaxed(&ctl->desc[s].seq) < later) {
+              // never seen: report it to the host, which stops serving with an error
+              __hip_atomic_store(&ctl->fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              if (open_count) report();
+              leave = true;
+              break;
+            }
+            nt_seq = held ? later : ~0ull;
+            ntiles = held ? lnt : 0;
+            if (held && (int64_t)wc < lnt) { got_seq = (int64_t)later; got_tile = (int64_t)wc; }
             else moved_on = true;
             break;
           }
-          if (got_seq >= 0) break;
+          if (got_seq >= 0 || leave) break;
           if (moved_on) {
             if (open_count && cur_seq == seq) report();  // leaving request seq
             ++seq;
@@ -168,6 +211,7 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
         cur.minkey = sys_relaxed(&d->minkey);
         cur.dmin = sys_relaxed(&d->dmin);
         cur.argmin = sys_relaxed(&d->argmin);
+        cur.Jmin = sys_relaxed(&d->Jmin);
         cur.want_grad = sys_relaxed(&d->want_grad);
         cur.seq = (uint64_t)got_seq;
         cur_seq = (uint64_t)got_seq;
@@ -187,6 +231,22 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
           fin.argmin[k] = key == ~0ull ? 0 : (int32_t)(uint32_t)(key & 0xffffffffu);
           fin.minkey[k] = ~0ull;
         }
+      }
+      if (fin.Jmin) {
+        // J at the argmin pairs (knot k, point argmin[k]): the pair-list tiles of
+        // gcdf_query's Jmin pass, run by this workgroup
+        __threadfence();
+        __syncthreads();  // every argmin written above is visible to the workgroup
+        Job pj{};
+        pj.knots = fin.knots;
+        pj.points = fin.points;
+        pj.K = fin.K;
+        pj.Np = fin.Np;
+        pj.pidx32 = fin.argmin;
+        pj.npairs = fin.K;
+        pj.J = fin.Jmin;
+        for (int64_t q0 = 0; q0 < fin.K; q0 += kTileQ)
+          process_tile<W, MODE, true, false, false, SPH>(net, pj, 1, 0, q0, tc);
       }
       __threadfence_system();
       __syncthreads();

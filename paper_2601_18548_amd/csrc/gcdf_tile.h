@@ -927,7 +927,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
         pi = job.csr_idx[qc];
       } else {
         ki = job.kidx ? job.kidx[qc] : qc;
-        pi = job.pidx ? job.pidx[qc] : qc;
+        pi = job.pidx32 ? (int64_t)job.pidx32[qc] : (job.pidx ? job.pidx[qc] : qc);
       }
     } else {
       ki = kk;
@@ -1067,6 +1067,15 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       __builtin_nontemporal_store(e[0] * x[1] - e[1] * x[0], Jo + 2);
 #pragma unroll
       for (int c = 3; c < 9; ++c) __builtin_nontemporal_store(e[c], Jo + c);
+      if constexpr (rev_arith<MODE>() == kF16) {
+        // a finite distance with a non-finite gradient: the FP16 reverse sweep
+        // overflowed (the forward is FP32-accumulated); flag it for the host
+        float t = 0.f;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) t += e[c];
+        if (!__builtin_isfinite(t) && __builtin_isfinite(dv) && net.overflow)
+          __hip_atomic_store(net.overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
     if constexpr (!PAIRS) {
       if (job.minkey) {

@@ -119,6 +119,13 @@ def _make_function():
             _checked(params, "params")
             _checked(knots, "knots")
             _checked(points, "points")
+            B = knots.shape[0]
+            if knots.dim() != 2 or knots.shape[1] != 9 or tuple(points.shape) != (B, 3):
+                raise ValueError("knots must be (B, 9) and points (B, 3)")
+            if params.numel() != param_count(trainer.width):
+                raise ValueError("params must hold %d floats" % param_count(trainer.width))
+            if B > trainer.max_batch:
+                raise ValueError("batch %d exceeds the trainer's max_batch %d" % (B, trainer.max_batch))
             d = trainer.forward(params, knots, points)
             ctx.save_for_backward(params, knots, points)
             ctx.trainer = trainer

@@ -245,3 +245,34 @@ def test_fp16_reverse_sweep_with_large_back_propagated_values(gcdf, oracle_mod):
     dd, rj = np.abs(d - dr), rel_j_err(J, Jr)
     report("large reverse values", dd, rj)
     assert dd.max() <= 100 * 1e-3 and rj.max() <= 1e-2
+
+
+def test_fp16_reverse_overflow_is_reported(gcdf):
+    """Output weights 10,000x larger back-propagate values of ~3e3 (~2e5 after the
+    2^6 scale, past FP16's 65,504): J overflows while d stays finite.  The next
+    query call on the context reports GCDF_ERANGE once, without launching; the call
+    after it runs normally.  The BF16X2 context of the same network never flags."""
+    w = wl.weights(512, seed=3)
+    w.mats[4] = (w.mats[4] * 1.0e4).astype(np.float32)
+    k = wl.knots(4, 33)
+    p = wl.points_patches(300, 34)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    print("case FP16 overflow: width 512 bf16x2_f16 K=4 Np=300", flush=True)
+    ctx = gcdf.Context(w.to_blob(), 512, "bf16x2_f16")
+    d, J = ctx.eval_grad(kt, pt)
+    torch.cuda.synchronize()
+    assert torch.isfinite(d).all() and not torch.isfinite(J).all()
+    with pytest.raises(gcdf.GcdfError) as e:
+        ctx.eval(kt, pt)
+    assert e.value.status == gcdf.ERANGE
+    d2 = ctx.eval(kt, pt)  # the flag was cleared by the report
+    torch.cuda.synchronize()
+    assert torch.equal(d2, d)
+    ref = gcdf.Context(w.to_blob(), 512, "bf16x2")
+    _, J3 = ref.eval_grad(kt, pt)
+    torch.cuda.synchronize()
+    assert torch.isfinite(J3).all()
+    ref.eval(kt, pt)
+    torch.cuda.synchronize()
+    ctx.close()
+    ref.close()

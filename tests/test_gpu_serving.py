@@ -27,19 +27,20 @@ def gcdf():
 
 
 class Req:
-    def __init__(self, K, Np, seed, outputs=("d", "J", "min")):
+    def __init__(self, K, Np, seed, outputs=("d", "J", "min", "jmin")):
         self.k = torch.from_numpy(wl.knots(K, seed)).cuda()
         self.p = torch.from_numpy(wl.points_patches(Np, seed + 1)).cuda()
         self.d = torch.full((K, Np), float("nan"), device="cuda") if "d" in outputs else None
         self.J = torch.full((K, Np, 9), float("nan"), device="cuda") if "J" in outputs else None
         self.dmin = torch.full((K,), float("nan"), device="cuda") if "min" in outputs else None
         self.am = torch.full((K,), -7, dtype=torch.int32, device="cuda") if "min" in outputs else None
+        self.Jm = torch.full((K, 9), float("nan"), device="cuda") if "jmin" in outputs else None
 
     def submit(self, ctx):
-        return ctx.submit(self.k, self.p, self.d, self.J, self.dmin, self.am)
+        return ctx.submit(self.k, self.p, self.d, self.J, self.dmin, self.am, self.Jm)
 
     def arrays(self):
-        return [None if t is None else t.cpu().numpy() for t in (self.d, self.J, self.dmin, self.am)]
+        return [None if t is None else t.cpu().numpy() for t in (self.d, self.J, self.dmin, self.am, self.Jm)]
 
 
 def wait_all(ctx, tickets, timeout=60.0):
@@ -54,10 +55,11 @@ def wait_all(ctx, tickets, timeout=60.0):
 
 
 def reference(ctx_q, r):
+    """The one-shot calls' d, J, dmin, argmin and Jmin (gcdf_knot_min's)."""
     d, J = ctx_q.eval_grad(r.k, r.p)
-    dmin, am = ctx_q.knot_min(r.k, r.p)
+    dmin, am, Jm = ctx_q.knot_min(r.k, r.p, with_jacobian=True)
     torch.cuda.synchronize()
-    return [d.cpu().numpy(), J.cpu().numpy(), dmin.cpu().numpy(), am.cpu().numpy()]
+    return [d.cpu().numpy(), J.cpu().numpy(), dmin.cpu().numpy(), am.cpu().numpy(), Jm.cpu().numpy()]
 
 
 @pytest.fixture(scope="module")
@@ -116,7 +118,7 @@ def test_results_match_oracle_on_samples(gcdf, oracle_mod, weights):
 def test_memory_budget_admission_and_errors(gcdf, weights):
     # budget fits one of these requests at a time: they must still all finish
     r0 = Req(40, 3000, 11)
-    per_req = 40 * 36 + 3000 * 12 + 40 * 3000 * 40 + 40 * 16
+    per_req = 40 * 36 + 3000 * 12 + 40 * 3000 * 40 + 40 * 16 + 40 * 36
     srv = gcdf.Context(weights.to_blob(), 256, "bf16x2", serve_mem_budget=int(per_req * 1.5), serve_slots=4)
     reqs = [r0] + [Req(40, 3000, 12 + i) for i in range(3)]
     wait_all(srv, [r.submit(srv) for r in reqs])
@@ -176,4 +178,33 @@ def test_other_widths_and_precisions_match_one_shot(gcdf, width, precision):
     for r in first + [late]:
         for a, b in zip(r.arrays(), reference(one, r)):
             assert np.array_equal(a, b)
+    srv.close()
+
+
+@pytest.mark.parametrize("slots", [2, 3, 4])
+def test_many_small_requests_through_few_slots(gcdf, weights, slots):
+    """Far more requests in flight than slots, small and uneven (1-7 knots, 1-300
+    points: a few tiles each), so slots are reused while workgroups whose cursors
+    lag still walk past the completed requests; every result bitwise equal to the
+    one-shot calls, within a host-side deadline."""
+    print("case many small requests, slots=%d" % slots, flush=True)
+    srv = gcdf.Context(weights.to_blob(), 256, "bf16x2_f16", serve_mem_budget=2 * GiB, serve_slots=slots)
+    one = gcdf.Context(weights.to_blob(), 256, "bf16x2_f16")
+    rng = np.random.default_rng(40 + slots)
+    reqs = [Req(int(rng.integers(1, 8)), int(rng.integers(1, 301)), 300 + 7 * i) for i in range(96)]
+    wait_all(srv, [r.submit(srv) for r in reqs], timeout=30.0)
+    for r in reqs:
+        for a, b in zip(r.arrays(), reference(one, r)):
+            assert np.array_equal(a, b)
+    srv.close()
+
+
+def test_jmin_needs_the_minimum(gcdf, weights):
+    srv = gcdf.Context(weights.to_blob(), 256, "bf16x2", serve_mem_budget=GiB, serve_slots=2)
+    r = Req(4, 100, 70)
+    with pytest.raises(gcdf.GcdfError) as e:
+        srv.submit(r.k, r.p, r.d, r.J, None, None, r.Jm)
+    assert e.value.status == gcdf.EINVAL
+    with pytest.raises(ValueError):  # argmin of the wrong dtype never reaches the library
+        srv.submit(r.k, r.p, r.d, r.J, r.dmin, r.dmin, r.Jm)
     srv.close()

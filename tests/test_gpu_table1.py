@@ -66,6 +66,48 @@ def test_loss_and_gradient_match_oracle(tr_mod, oracle_mod):
         assert err <= 1e-5, name
 
 
+def test_loss_and_gradient_match_oracle_multi_chunk(tr_mod, oracle_mod):
+    """6,181 samples: 4 weight-gradient GEMM chunks of 2,048 (the second product
+    accumulated into the first), 13 row-reduction chunks of 512, a ragged last
+    tile; against the oracle's straight sums, then central differences of the
+    GPU's own loss."""
+    w = wl.weights(256, seed=86, bf16_hidden=False)
+    B = 6181
+    k, p, fs, Js = _case(B, 9)
+    tr = tr_mod.Trainer(256, "fp32", max_batch=B)
+    params = tr_mod.flat_params(w)
+    kt, pt, ft, Jt = _cuda(k, p, fs, Js)
+    print("case Table I multi-chunk B=%d" % B, flush=True)
+    losses, g = tr.table1(params, kt, pt, ft, Jt, M_DIAG)
+    torch.cuda.synchronize()
+    total, L, gref = oracle_mod.table1_grad(w.to_blob(), k, p, fs, Js, M_DIAG)
+    lg = losses.cpu().numpy()
+    print("losses gpu", lg, "oracle", L, total, flush=True)
+    np.testing.assert_allclose(lg[:4], L, rtol=1e-4)
+    assert lg[4] == pytest.approx(total, rel=1e-4)
+    gn = g.cpu().numpy()
+    for name, a, b in zip(NAMES, _split(gn, w), gref):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("B=%d %-5s rel err %.2e" % (B, name, err), flush=True)
+        assert err <= 1e-5, name
+    # central differences of the device loss (FP32 sums over 6,181 samples)
+    picks, off = [], 0
+    for a in w.flat_params():
+        seg = np.abs(gn[off:off + a.size])
+        picks.append(off + int(np.argmax(seg)))
+        off += a.size
+    h = 2e-3
+    for i in picks:
+        pp, pm = params.clone(), params.clone()
+        pp[i] += h
+        pm[i] -= h
+        lp = float(tr.table1(pp, kt, pt, ft, Jt, M_DIAG)[0][4])
+        lm = float(tr.table1(pm, kt, pt, ft, Jt, M_DIAG)[0][4])
+        fd = (lp - lm) / (2 * h)
+        print("FD param %d: fd %.6e grad %.6e" % (i, fd, gn[i]), flush=True)
+        assert abs(fd - gn[i]) <= 5e-3 * abs(gn[i]) + 2e-6 * abs(float(lg[4])) / h, (i, fd, gn[i])
+
+
 def test_value_term_alone_equals_mse_gradient(tr_mod):
     w = wl.weights(256, seed=82, bf16_hidden=False)
     B = 1000

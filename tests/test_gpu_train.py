@@ -65,6 +65,54 @@ def test_weight_gradients_match_oracle(tr_mod, oracle_mod, precision, tol):
         assert err <= tol, name
 
 
+# A batch past the chunk sizes of the reductions: 4 weight-gradient GEMM chunks of
+# 2,048 samples (the last one 37), 13 row-reduction chunks of 512 (the last 37),
+# and a ragged last tile of 37 samples.
+MULTI_B = 6181
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_weight_gradients_match_oracle_multi_chunk(tr_mod, oracle_mod, precision, tol):
+    """The chunked sums (GEMM chunks added in order, row-reduction chunks added in
+    order) against the oracle's straight sum over all 6,181 samples."""
+    w = wl.weights(256, seed=38, bf16_hidden=False)
+    k, p, y = batch(MULTI_B, 13)
+    print("case multi-chunk B=%d %s" % (MULTI_B, precision), flush=True)
+    _, _, _, _, d, g = gpu_grads(tr_mod, precision, w, k, p, y)
+    loss_ref, gref = oracle_mod.mse_grad(w.to_blob(), k.astype(np.float64), p.astype(np.float64), y)
+    for name, a, b in zip(NAMES, split(g, w), gref):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("%s B=%d %-5s rel err %.2e" % (precision, MULTI_B, name, err), flush=True)
+        assert np.all(np.isfinite(a))
+        assert err <= tol, name
+
+
+def test_gradient_matches_finite_differences_multi_chunk(tr_mod):
+    """Central differences of the GPU's own FP32 MSE loss at the multi-chunk batch."""
+    w = wl.weights(256, seed=39, bf16_hidden=False)
+    k, p, y = batch(MULTI_B, 14)
+    trainer, params, kt, pt, d, g = gpu_grads(tr_mod, "fp32", w, k, p, y)
+    yt = torch.from_numpy(y).cuda()
+
+    def loss(pv):
+        dd = trainer.forward(pv, kt, pt).double()
+        return float(((dd - yt.double()) ** 2).mean())
+
+    # the largest components of every parameter array, so each reduction path is hit
+    picks, off = [], 0
+    for a in w.flat_params():
+        seg = np.abs(g[off:off + a.size])
+        picks += [off + int(i) for i in np.argsort(-seg)[:2]]
+        off += a.size
+    h = 1e-3
+    for i in picks:
+        pp, pm = params.clone(), params.clone()
+        pp[i] += h
+        pm[i] -= h
+        fd = (loss(pp) - loss(pm)) / (2 * h)
+        assert abs(fd - g[i]) <= 2e-3 * abs(g[i]) + 1e-5, (i, fd, g[i])
+
+
 def test_backward_is_deterministic(tr_mod):
     w = wl.weights(256, seed=32, bf16_hidden=False)
     k, p, y = batch(2048 + 37, 4)
