@@ -81,6 +81,64 @@ def measured_traffic(launch_pairs: int, precision: str):
     return t.get("hbm_bytes_per_launch")
 
 
+def _pmc_per_dispatch(directory: str, counter: str, kernel_prefix: str):
+    """Per-dispatch values of one counter (summed over its instances) from a
+    rocprofv3 --output-format csv run, for dispatches of kernels whose name
+    starts with kernel_prefix."""
+    import csv
+    import glob
+
+    per = {}
+    for f in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter and row["Kernel_Name"].startswith(kernel_prefix):
+                    per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    return [per[k] for k in sorted(per, key=int)]
+
+
+def write_traffic_record(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, width=512, precision="bf16x2_f16"):
+    """HBM bytes per launch of the benchmark's fused kernel: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) scaled by what they read for 5 plain copies of
+    1 GiB, keyed to the kernel code they were taken on."""
+    kern = "void gcdf::fused_query<%d, %d, false, 1, false, false, false>" % (width, {"bf16x2_f16": 3, "bf16x2": 2}[precision])
+    fetch = _pmc_per_dispatch(fetch_dir, "FETCH_SIZE", kern)
+    write = _pmc_per_dispatch(write_dir, "WRITE_SIZE", kern)
+    cf = _pmc_per_dispatch(cal_fetch_dir, "FETCH_SIZE", "__amd_rocclr_copyBuffer")
+    cw = _pmc_per_dispatch(cal_write_dir, "WRITE_SIZE", "__amd_rocclr_copyBuffer")
+    if not (fetch and write and cf and cw):
+        raise SystemExit("missing counter rows")
+    nbytes = 1 << 30
+    ff = nbytes / (sum(cf) / len(cf) * 1024)
+    fw = nbytes / (sum(cw) / len(cw) * 1024)
+    rd = sum(fetch) / len(fetch) * 1024 * ff
+    wr = sum(write) / len(write) * 1024 * fw
+    rec = {"kernel": "fused_query<%d, %s> (dense, d + J + per-knot min)" % (width, precision.upper()),
+           "precision": precision, "kernel_code_sha256_16": kernel_source_hash(),
+           "pairs_per_launch": 128 * 16384,
+           "fetch_size_kib_per_dispatch": fetch, "write_size_kib_per_dispatch": write,
+           "copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes,
+                                "fetch_size_kib": sum(cf) / len(cf), "write_size_kib": sum(cw) / len(cw),
+                                "fetch_factor": ff, "write_factor": fw},
+           "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr, "hbm_bytes_per_launch": rd + wr,
+           "algorithmic_bytes_per_launch": {"inputs": 128 * 36 + 16384 * 12,
+                                            "packed_weights_once": 6 * width * width * 2 + width * 4 * 16,
+                                            "outputs": 128 * 16384 * 40},
+           "commands": [
+               "rocprofv3 --pmc %s -d $R/gpurun_out/<dir> -o p --output-format csv -- python3 $R/bench.py "
+               "--steps 3 --warmup 1 --no-cpu-baseline --no-modes --serve-requests 0 --train-steps 0 "
+               "--no-constraints --no-sphere   (once with FETCH_SIZE, once with WRITE_SIZE)" % "<counter>",
+               "rocprofv3 --pmc <counter> -d $R/gpurun_out/<dir> -o p --output-format csv -- python3 $R/bench.py "
+               "--copy-calibration 1024   (FETCH_SIZE, then WRITE_SIZE)",
+               "python3 bench.py --traffic-from <FETCH_SIZE dir> <WRITE_SIZE dir> <copy FETCH_SIZE dir> "
+               "<copy WRITE_SIZE dir>"],
+           "run_from": "/tmp with TMPDIR=/tmp, R = repository root; the plain copy is torch's Tensor.copy_ of "
+                       "1 GiB (the HIP runtime's copy kernel)"}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"hbm_read_MB": rd / 1e6, "hbm_write_MB": wr / 1e6}))
+
+
 def time_mode(g, torch, wk, precision, steps, warmup, keep_outputs=False):
     """Returns (seconds per step for gcdf_query, mean fused-kernel ms from events),
     plus the last launch's d and J (device tensors) with keep_outputs."""
@@ -426,7 +484,14 @@ def main():
     ap.add_argument("--no-sphere", action="store_true", help="skip the sphere-obstacle leg")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="write the HBM traffic record from the CSV output of four rocprofv3 --pmc runs "
+                         "(FETCH_SIZE and WRITE_SIZE of this benchmark's short run, then of "
+                         "--copy-calibration 1024) and exit; needs no GPU")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic_record(*args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py: measures one GPU only (the query shards by knots or points "
               "with no exchange but a K-value min all-reduce); run with --gpus 1", file=sys.stderr)

@@ -33,7 +33,8 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
   constexpr int MT = G::MT;
   constexpr int XF = G::XIN_FLOATS;
   __shared__ __attribute__((aligned(16))) char lds[G::LDS_BYTES];
-  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
+  __shared__ uint32_t ovf;  // (FP32: never set)
+  TileCtx<W, MODE> tc(lds, &ovf, net, threadIdx.x);
   const Lane<W, MODE>& ln = tc.ln;
   const Bases<W, MODE>& b = tc.b;
   float* uin = tc.red;  // [64][9] tangent direction of the tile's samples

@@ -48,7 +48,8 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
   __shared__ int64_t claim_info[3];  // claimed seq (or -1: exit, -2: none), tile, seq to finalize (or -1)
   __shared__ ServeDesc cur;          // the request this workgroup is working on
   __shared__ ServeDesc fin;          // a request this workgroup completes
-  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
+  __shared__ uint32_t ovf;
+  TileCtx<W, MODE> tc(lds, &ovf, net, threadIdx.x);
   const int tid = threadIdx.x;
   uint64_t seq = first_seq;  // this workgroup's cursor in the request sequence
   uint64_t cur_seq = ~0ull;
@@ -268,6 +269,7 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), 1) void serve_loop(const D
     process_tile<W, MODE, false, false, false, SPH>(net, job, cur.want_grad, kk, (t - kk * cur.nblk) * kTileQ, tc);
     if (tid == 0) idle_since = __builtin_amdgcn_s_memrealtime();
   }
+  report_overflow<W, MODE>(net, tc);
 }
 
 template <int W, int MODE, bool SPH>

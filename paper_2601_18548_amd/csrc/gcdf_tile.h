@@ -855,10 +855,12 @@ struct TileCtx {
   float* xin;   // [64][16]
   float* crow;  // [W]
   float* red;   // [waves][10][64]
+  uint32_t* ovf;  // LDS word: a tile of this workgroup overflowed FP16 (see report_overflow)
   Lane<W, MODE> ln;
   Bases<W, MODE> b;
-  __device__ __forceinline__ TileCtx(char* lds, const DevNet& net, int tid)
-      : act(lds), ln(lds, tid) {
+  __device__ __forceinline__ TileCtx(char* lds, uint32_t* ovf_word, const DevNet& net, int tid)
+      : act(lds), ovf(ovf_word), ln(lds, tid) {
+    if (tid == 0) *ovf = 0u;  // ordered before any tile's use by the tile's first barrier
     using G = Geo<W, MODE>;
     constexpr int MT = G::MT;
     xin = reinterpret_cast<float*>(lds + G::ACT_BYTES);
@@ -1009,6 +1011,22 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td);
     bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td);
     bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td);
+    if constexpr (rev_arith<MODE>() == kF16) {
+      // a lane whose output partial sum is finite but whose input-gradient partial
+      // sums are not: the FP16 reverse sweep overflowed (the forward accumulates in
+      // FP32; a non-finite input point makes every partial non-finite).  Noted in
+      // LDS, reported to the host once per workgroup when the kernel ends
+      // (report_overflow).
+      uint32_t bad = 0;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        float t = 0.f;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) t += epart[nt][c];
+        bad |= (uint32_t)(!__builtin_isfinite(t)) & (uint32_t)__builtin_isfinite(dpart[nt]);
+      }
+      if (bad) *tc.ovf = 1u;
+    }
   }
 
   // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
@@ -1067,15 +1085,6 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       __builtin_nontemporal_store(e[0] * x[1] - e[1] * x[0], Jo + 2);
 #pragma unroll
       for (int c = 3; c < 9; ++c) __builtin_nontemporal_store(e[c], Jo + c);
-      if constexpr (rev_arith<MODE>() == kF16) {
-        // a finite distance with a non-finite gradient: the FP16 reverse sweep
-        // overflowed (the forward is FP32-accumulated); flag it for the host
-        float t = 0.f;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) t += e[c];
-        if (!__builtin_isfinite(t) && __builtin_isfinite(dv) && net.overflow)
-          __hip_atomic_store(net.overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
     }
     if constexpr (!PAIRS) {
       if (job.minkey) {
@@ -1095,6 +1104,17 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   __syncthreads();
 }
 
+// End of a kernel that ran tiles: if any tile of this workgroup flagged an FP16
+// overflow, write the context's host-visible flag (all threads call it).
+template <int W, int MODE>
+__device__ __forceinline__ void report_overflow(const DevNet& net, const TileCtx<W, MODE>& tc) {
+  if constexpr (rev_arith<MODE>() == kF16) {
+    __syncthreads();
+    if (threadIdx.x == 0 && *tc.ovf && net.overflow)
+      __hip_atomic_store(net.overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // One-shot kernel: a persistent grid strides over all tiles of one job.
 // ----------------------------------------------------------------------------
@@ -1102,7 +1122,8 @@ template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false, bool GATHER 
 __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
   __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES];
-  TileCtx<W, MODE> tc(lds, net, threadIdx.x);
+  __shared__ uint32_t ovf;
+  TileCtx<W, MODE> tc(lds, &ovf, net, threadIdx.x);
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (PAIRS) {
@@ -1121,6 +1142,7 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(cons
       process_tile<W, MODE, false, false, false, SPH>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
     }
   }
+  report_overflow<W, MODE>(net, tc);
 }
 
 // ----------------------------------------------------------------------------

@@ -103,7 +103,7 @@ def test_results_match_oracle_on_samples(gcdf, oracle_mod, weights):
     srv = gcdf.Context(weights.to_blob(), 256, "bf16x2", serve_mem_budget=4 * GiB, serve_slots=8)
     r = Req(17, 777, 9)
     wait_all(srv, [r.submit(srv)])
-    d, J, dmin, am = r.arrays()
+    d, J, dmin, am, Jm = r.arrays()
     k, p = r.k.cpu().numpy(), r.p.cpu().numpy()
     ki = np.arange(17).repeat(8)
     pi = np.random.default_rng(2).integers(0, 777, len(ki))
@@ -112,6 +112,11 @@ def test_results_match_oracle_on_samples(gcdf, oracle_mod, weights):
     nr = np.linalg.norm(Jr, axis=1)
     assert (np.linalg.norm(J[ki, pi] - Jr, axis=1) / np.maximum(nr, 1e-3 * np.median(nr))).max() <= 1e-2
     assert np.array_equal(dmin, d.min(axis=1)) and np.array_equal(am, d.argmin(axis=1))
+    # J at the argmin against the oracle's J of the same pairs
+    dm_r, Jm_r = oracle_mod.eval_pairs(weights.to_blob(), k, p, np.arange(17), am)
+    assert np.abs(dmin - dm_r).max() <= 1e-3
+    nm = np.linalg.norm(Jm_r, axis=1)
+    assert (np.linalg.norm(Jm - Jm_r, axis=1) / np.maximum(nm, 1e-3 * np.median(nr))).max() <= 1e-2
     srv.close()
 
 
