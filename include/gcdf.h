@@ -149,6 +149,21 @@ gcdf_status gcdf_knot_min(gcdf_ctx* ctx, const float* knots, int64_t K, const fl
 gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
                        float* d, float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream);
 
+/* gcdf_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same outputs, bitwise, from the same kernels, but the per-knot minimum keys
+ * live in a fixed array of 65,536 keys (512 KiB) that the library holds on
+ * each GPU until the process ends, instead of the context's workspace.  The
+ * call allocates nothing.  Every call on one GPU (from any context) shares that
+ * GPU's array, which keeps the last call's contents; the minimum clears the
+ * keys it uses before each launch, so consecutive calls are independent, but
+ * calls that overlap on one GPU (other streams or threads) race and may
+ * return wrong minima.  Arguments, layout and ownership as gcdf_query.
+ * EINVAL as gcdf_query, and when the minimum is requested with K > 65,536;
+ * EDEVICE if the array has no device address on the context's device. */
+gcdf_status gcdf_query_noalloc(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                               float* d, float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Obstacle partitions and the sparse constraint Jacobian.                   */
 /*                                                                           */

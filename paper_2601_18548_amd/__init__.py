@@ -68,6 +68,8 @@ def library() -> ctypes.CDLL:
     lib.gcdf_knot_min.restype = ctypes.c_int
     lib.gcdf_query.argtypes = [P, P, I64, P, I64, P, P, P, P, P, P]
     lib.gcdf_query.restype = ctypes.c_int
+    lib.gcdf_query_noalloc.argtypes = [P, P, I64, P, I64, P, P, P, P, P, P]
+    lib.gcdf_query_noalloc.restype = ctypes.c_int
     lib.gcdf_param_count.argtypes = [ctypes.c_int32]
     lib.gcdf_param_count.restype = ctypes.c_int64
     lib.gcdf_trainer_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, I64, ctypes.POINTER(P)]
@@ -105,7 +107,7 @@ def library() -> ctypes.CDLL:
 
 
 EXPORTED = ["gcdf_create", "gcdf_destroy", "gcdf_last_error", "gcdf_eval", "gcdf_eval_grad",
-            "gcdf_knot_min", "gcdf_query", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
+            "gcdf_knot_min", "gcdf_query", "gcdf_query_noalloc", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
             "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward",
             "gcdf_partition_count", "gcdf_partition_fill", "gcdf_eval_grad_csr", "gcdf_jacobian_pattern",
             "gcdf_project", "gcdf_project_csr", "gcdf_adam_step", "gcdf_train_table1"]
@@ -240,8 +242,11 @@ class Context:
                                        _stream(stream)), self._h)
         return (dmin, am, Jm) if with_jacobian else (dmin, am)
 
-    def query(self, knots, points, d=None, J=None, dmin=None, argmin=None, Jmin=None, stream=None):
-        """All requested outputs from one fused pass (preallocated tensors or None)."""
+    def query(self, knots, points, d=None, J=None, dmin=None, argmin=None, Jmin=None, stream=None,
+              noalloc: bool = False):
+        """All requested outputs from one fused pass (preallocated tensors or None).
+        noalloc: through gcdf_query_noalloc (the library's fixed per-GPU key array,
+        at most 65,536 knots with the minimum; calls on one GPU must not overlap)."""
         K, Np = knots.shape[0], points.shape[0]
         _need(knots, (K, 9), "knots")
         _need(points, (Np, self.obstacle_dim), "points")
@@ -252,8 +257,9 @@ class Context:
         if J is not None:
             _need(J, (K, Np, 9), "J", device=dev)
         _need_min(K, dmin, argmin, Jmin, dev)
-        _check(library().gcdf_query(self._h, _ptr(knots), K, _ptr(points), Np, _ptr(d), _ptr(J), _ptr(dmin),
-                                    _ptr(argmin), _ptr(Jmin), _stream(stream)), self._h)
+        fn = library().gcdf_query_noalloc if noalloc else library().gcdf_query
+        _check(fn(self._h, _ptr(knots), K, _ptr(points), Np, _ptr(d), _ptr(J), _ptr(dmin), _ptr(argmin), _ptr(Jmin),
+                  _stream(stream)), self._h)
         return d, J, dmin, argmin, Jmin
 
     # -- obstacle partitions and the sparse constraint Jacobian --------------

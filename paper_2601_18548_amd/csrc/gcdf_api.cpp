@@ -13,9 +13,23 @@
 #include "gcdf_internal.h"
 #include "gcdf_serve.h"
 
+#include <mutex>
+
 namespace {
 
 thread_local std::string g_err;
+
+// Per-knot minimum keys of gcdf_query_noalloc, which allocates nothing: a
+// file-scope device array, one copy per GPU (held until the process ends).  Its
+// name is only a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device (g_noalloc_keys).
+constexpr int64_t kNoAllocMaxKnots = 1 << 16;  // 512 KiB of keys
+static __device__ __align__(256) unsigned long long scratch[kNoAllocMaxKnots];
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned long long* g_noalloc_keys[kMaxDevices];  // device address of `scratch` per device
+hipError_t g_noalloc_err[kMaxDevices];            // hipGetSymbolAddress's result per device
+bool g_noalloc_done[kMaxDevices];
 
 gcdf_status fail(gcdf_status st, const char* fmt, ...) {
   char buf[512];
@@ -43,6 +57,8 @@ struct gcdf_ctx {
   void* wbuf = nullptr;               // all packed weights
   unsigned long long* minkey = nullptr;  // [max_knots]
   int64_t* tile_off = nullptr;        // [max_knots + 1] (CSR query)
+  unsigned long long* noalloc_keys = nullptr;  // this device's `scratch` (gcdf_query_noalloc)
+  hipError_t noalloc_err = hipSuccess;         // why noalloc_keys is NULL
   uint32_t* overflow = nullptr;       // pinned host word written by the device (GCDF_BF16X2_F16)
   gcdf::Server* server = nullptr;
 };
@@ -79,6 +95,24 @@ gcdf_status check_query(gcdf_ctx* ctx, const float* knots, int64_t K, const floa
   if (K <= 0 || Np <= 0) return fail(GCDF_EINVAL, "K and Np must be positive (K=%lld, Np=%lld)", (long long)K, (long long)Np);
   if (K > INT64_MAX / 9 / Np) return fail(GCDF_EINVAL, "K*Np*9 overflows int64");
   return GCDF_OK;
+}
+
+// Device address of `scratch` on device `dev`, which must be current: looked up
+// once per device (the first context created on it) and kept.
+unsigned long long* noalloc_keys_for(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_done[dev]) {
+    void* p = nullptr;
+    g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_keys[dev] = g_noalloc_err[dev] == hipSuccess ? static_cast<unsigned long long*>(p) : nullptr;
+    g_noalloc_done[dev] = true;
+  }
+  *err = g_noalloc_err[dev];
+  return g_noalloc_keys[dev];
 }
 
 }  // namespace
@@ -214,6 +248,9 @@ gcdf_status gcdf_create(const gcdf_config* cfg, const void* blob, size_t bytes, 
   c->net.bh = bh;
   c->net.w5 = w5;
   c->net.b5p = reinterpret_cast<const float*>(base + off_b5);
+  // the no-allocation entry point's key array on this device (only that entry
+  // point depends on it, so a failed lookup is reported there)
+  c->noalloc_keys = noalloc_keys_for(dev, &c->noalloc_err);
   if (mode == GCDF_BF16X2_F16) {
     e = hipHostMalloc(reinterpret_cast<void**>(&c->overflow), sizeof(uint32_t), hipHostMallocCoherent);
     if (e != hipSuccess) {
@@ -250,21 +287,25 @@ void gcdf_destroy(gcdf_ctx* ctx) {
   delete ctx;
 }
 
-gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
-                       float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream) {
-  gcdf_status st = check_query(ctx, knots, K, points, Np);
-  if (st != GCDF_OK) return st;
+}  // extern "C"
+
+namespace {
+// gcdf_query with the per-knot key array `keys` (capacity key_cap knots), which
+// the minimum clears (all ones) before use.
+gcdf_status query_impl(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
+                       float* J, float* dmin, int32_t* argmin, float* Jmin, unsigned long long* keys,
+                       int64_t key_cap, const char* cap_name, void* stream) {
   const bool want_min = dmin || argmin;
   if (!d && !J && !want_min) return fail(GCDF_EINVAL, "no output requested");
   if (want_min && !(dmin && argmin)) return fail(GCDF_EINVAL, "dmin and argmin must be given together");
   if (Jmin && !want_min) return fail(GCDF_EINVAL, "Jmin needs dmin and argmin");
-  if (want_min && K > ctx->cfg.max_knots)
-    return fail(GCDF_EINVAL, "K=%lld exceeds max_knots=%lld", (long long)K, (long long)ctx->cfg.max_knots);
+  if (want_min && K > key_cap)
+    return fail(GCDF_EINVAL, "K=%lld exceeds %s=%lld", (long long)K, cap_name, (long long)key_cap);
   if (want_min && Np > INT32_MAX) return fail(GCDF_EINVAL, "Np=%lld exceeds 2^31-1", (long long)Np);
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
-  if (want_min) e = gcdf::launch_minkey_init(ctx->minkey, K, s);
+  if (want_min) e = gcdf::launch_minkey_init(keys, K, s);
   gcdf::Job job{};
   job.knots = knots;
   job.points = points;
@@ -272,9 +313,9 @@ gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float
   job.Np = Np;
   job.d = d;
   job.J = J;
-  job.minkey = want_min ? ctx->minkey : nullptr;
+  job.minkey = want_min ? keys : nullptr;
   if (e == hipSuccess) e = gcdf::launch_fused(ctx->net, job, false, J != nullptr, ctx->num_cu, s);
-  if (e == hipSuccess && want_min) e = gcdf::launch_minkey_decode(ctx->minkey, K, dmin, argmin, s);
+  if (e == hipSuccess && want_min) e = gcdf::launch_minkey_decode(keys, K, dmin, argmin, s);
   if (e == hipSuccess && Jmin) {
     // the K pairs (knot i, point argmin[i]) through the pair-list kernel
     gcdf::Job pj{};
@@ -288,6 +329,28 @@ gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float
     e = gcdf::launch_fused(ctx->net, pj, true, true, ctx->num_cu, s);
   }
   return e == hipSuccess ? GCDF_OK : hip_fail(e, "gcdf_query launch");
+}
+}  // namespace
+
+extern "C" {
+
+gcdf_status gcdf_query(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
+                       float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream) {
+  gcdf_status st = check_query(ctx, knots, K, points, Np);
+  if (st != GCDF_OK) return st;
+  return query_impl(ctx, knots, K, points, Np, d, J, dmin, argmin, Jmin, ctx->minkey, ctx->cfg.max_knots,
+                    "max_knots", stream);
+}
+
+gcdf_status gcdf_query_noalloc(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np,
+                               float* d, float* J, float* dmin, int32_t* argmin, float* Jmin, void* stream) {
+  gcdf_status st = check_query(ctx, knots, K, points, Np);
+  if (st != GCDF_OK) return st;
+  if (!ctx->noalloc_keys)
+    return fail(GCDF_EDEVICE, "the no-allocation key array has no device address: %s",
+                hipGetErrorString(ctx->noalloc_err));
+  return query_impl(ctx, knots, K, points, Np, d, J, dmin, argmin, Jmin, ctx->noalloc_keys, kNoAllocMaxKnots,
+                    "the no-allocation limit", stream);
 }
 
 gcdf_status gcdf_eval(gcdf_ctx* ctx, const float* knots, int64_t K, const float* points, int64_t Np, float* d,
