@@ -18,7 +18,8 @@ Sec. IV-A (trajectory optimisation) of the paper:
 
 Readings where the paper is silent or garbled:
 
-* "within a certain range": planar Euclidean distance between the point's
+* the partition's range (the paper leaves its metric open): planar Euclidean
+  distance between the point's
   (x, y) and the reference base position, <= radius (z ignored).  The
   decision is taken in float32 exactly as written, dx*dx + dy*dy <= r*r with
   every operation rounded (no fused multiply-add), points in ascending

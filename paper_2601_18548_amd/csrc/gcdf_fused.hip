@@ -404,10 +404,8 @@ size_t packed_matrix_bytes(int width, int mode) {
 // (exact for magnitudes in [2^-17, 65504], the range gcdf_create admits).  Element e
 // of lane (m, kh) in K step kb is column 16 kb + 8 kh + e, or with lane_order
 // 16 kb + 8 (e / 4) + 4 kh + e % 4 (the order the split modes keep activations in).
-__global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int W, int transpose,
-                                 int to_f16, int lane_order) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)W * W) return;
+__device__ __forceinline__ void pack_bf16_elem(const float* __restrict__ src, uint16_t* __restrict__ dst, int W,
+                                               int64_t idx, int transpose, int to_f16, int lane_order) {
   const int MT = W / (32 * kWaves), NKB = W / 16;
   const int e = idx & 7;
   const int lane = (idx >> 3) & 63;
@@ -422,9 +420,14 @@ __global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __rest
   dst[idx] = to_f16 ? __builtin_bit_cast(uint16_t, (_Float16)(float)vb) : __builtin_bit_cast(uint16_t, vb);
 }
 
-__global__ void pack_fp32_kernel(const float* __restrict__ src, float* __restrict__ dst, int W, int transpose) {
+__global__ void pack_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int W, int transpose,
+                                 int to_f16, int lane_order) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)W * W) return;
+  if (idx < (int64_t)W * W) pack_bf16_elem(src, dst, W, idx, transpose, to_f16, lane_order);
+}
+
+__device__ __forceinline__ void pack_fp32_elem(const float* __restrict__ src, float* __restrict__ dst, int W,
+                                               int64_t idx, int transpose) {
   const int MT = W / (32 * kWaves), NK8 = W / 8;
   const int q = idx & 3;
   const int lane = (idx >> 2) & 63;
@@ -435,6 +438,11 @@ __global__ void pack_fp32_kernel(const float* __restrict__ src, float* __restric
   const int row = 32 * (wave * MT + i) + (lane & 31);
   const int col = 8 * j + 2 * q + (lane >> 5);
   dst[idx] = transpose ? src[(int64_t)col * W + row] : src[(int64_t)row * W + col];
+}
+
+__global__ void pack_fp32_kernel(const float* __restrict__ src, float* __restrict__ dst, int W, int transpose) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)W * W) pack_fp32_elem(src, dst, W, idx, transpose);
 }
 
 hipError_t pack_matrix(const float* src, void* dst, int width, int mode, bool transpose, hipStream_t s) {
@@ -473,6 +481,52 @@ __global__ void pack_input_kernel(const float* __restrict__ W1, const float* __r
   for (int c = 0; c < 6; ++c) o[4 + c] = w[arm0 + c];
   o[10] = in_dim == kInDimSphere ? w[3] : 0.f;  // radius column
   o[11] = 0.f;
+}
+
+// Every packed array of a network in one launch: blockIdx.y = 0..5 the hidden
+// matrices (y < 3: W_{y+2}, else W_{y-1}^T), 6 the row vectors b2, b3, b4, w_out,
+// 7 the input layer; each block packs 256 elements.
+__global__ __launch_bounds__(256) void pack_all_kernel(PackJob pj) {
+  const int W = pj.width;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (y < 6) {
+    if (idx >= (int64_t)W * W) return;
+    const int l = y % 3;
+    const bool tr = y >= 3;
+    if (pj.mode == kFP32) {
+      pack_fp32_elem(pj.Wl[l], static_cast<float*>(tr ? pj.bwd[l] : pj.fwd[l]), W, idx, tr ? 1 : 0);
+    } else {
+      pack_bf16_elem(pj.Wl[l], static_cast<uint16_t*>(tr ? pj.bwd[l] : pj.fwd[l]), W, idx, tr ? 1 : 0,
+                     (tr && pj.mode == kBF16X2F16) ? 1 : 0, (pj.mode == kBF16X2 || pj.mode == kBF16X2F16) ? 1 : 0);
+    }
+  } else if (y == 6) {
+    if (idx >= 4 * (int64_t)W) return;
+    const int v = (int)(idx / W), r = (int)(idx % W);
+    const float* src = v < 3 ? pj.bl[v] : pj.w5;
+    float* dst = v < 3 ? pj.bh + (size_t)v * W : pj.w5p;
+    dst[lane_major_pos(r, W)] = src[r];
+  } else {
+    if (idx >= W) return;
+    const int r = (int)idx;
+    const float* w = pj.W1 + (size_t)r * pj.in_dim;
+    const int arm0 = pj.in_dim - 6;
+    float* o = pj.w1p + lane_major_pos(r, W) * 12;
+    o[0] = w[0];
+    o[1] = w[1];
+    o[2] = w[2];
+    o[3] = pj.b1[r];
+    for (int c = 0; c < 6; ++c) o[4 + c] = w[arm0 + c];
+    o[10] = pj.in_dim == kInDimSphere ? w[3] : 0.f;
+    o[11] = 0.f;
+  }
+}
+
+hipError_t pack_network(const PackJob& pj, hipStream_t s) {
+  if (pj.in_dim != kInDim && pj.in_dim != kInDimSphere) return hipErrorInvalidValue;
+  const unsigned bx = (unsigned)(((int64_t)pj.width * pj.width + 255) / 256);
+  hipLaunchKernelGGL(pack_all_kernel, dim3(bx, 8), dim3(256), 0, s, pj);
+  return hipGetLastError();
 }
 
 hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int width, int in_dim, hipStream_t s) {
@@ -821,6 +875,118 @@ hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B,
   const int64_t n = (int64_t)rows * (kRrMaxC + 1);
   hipLaunchKernelGGL(rr_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nch, rows, C, out,
                      bias, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+// Several row reductions in one pass each (see RrJobs): grid (row group, chunk,
+// job); job j's partial sums at partial + j * job_stride in the layout of
+// rr_partial_kernel.  A job without A reduces a single row of ones (out = sum V).
+template <bool BF>
+__global__ __launch_bounds__(256) void rr_multi_partial_kernel(RrJobs jobs, int64_t B, int64_t ldv,
+                                                               float* __restrict__ partial, int64_t job_stride) {
+  constexpr int S = BF ? 8 : 4;
+  __shared__ float sv[kRrMaxC][kRrChunk];
+  const RrJob& jb = jobs.job[blockIdx.z];
+  const int rows = jb.A ? jb.rows : 1, C = jb.C;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= rows) return;  // a whole workgroup past this job's rows
+  const int64_t i0 = (int64_t)blockIdx.y * kRrChunk;
+  const int64_t i1 = i0 + kRrChunk < B ? i0 + kRrChunk : B;
+  for (int c = 0; c < C; ++c)
+    for (int k = threadIdx.x; k < kRrChunk; k += 256) sv[c][k] = i0 + k < i1 ? jb.V[(int64_t)c * ldv + i0 + k] : 0.f;
+  __syncthreads();
+  if (r >= rows) return;
+  float acc[kRrMaxC + 1];
+#pragma unroll
+  for (int c = 0; c <= kRrMaxC; ++c) acc[c] = 0.f;
+  constexpr int NB = 8;
+  typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
+  for (int64_t i = i0; i < i1; i += NB * S) {
+    float a[NB][S];
+    // rounds stay inside the zero-padded tail, as in rr_partial_kernel
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (!jb.A) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) a[k][u] = 1.f;  // V is zero past B
+        continue;
+      }
+      const int64_t blk = (((i + k * S) / S) * rows + r) * S;
+      if constexpr (BF) {
+        const v8 x = *reinterpret_cast<const v8*>(static_cast<const __bf16*>(jb.A) + blk);
+#pragma unroll
+        for (int u = 0; u < S; ++u) a[k][u] = (float)x[u];
+      } else {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(static_cast<const float*>(jb.A) + blk);
+#pragma unroll
+        for (int u = 0; u < S; ++u) a[k][u] = x[u];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+      for (int u = 0; u < S; ++u) acc[kRrMaxC] += a[k][u];
+    const int j0 = (int)(i - i0);
+    for (int c = 0; c < C; ++c) {
+      float t = acc[c];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const f32x4* vp = reinterpret_cast<const f32x4*>(&sv[c][j0 + k * S]);
+#pragma unroll
+        for (int h = 0; h < S / 4; ++h) {
+          const f32x4 vv = vp[h];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) t += a[k][4 * h + u] * vv[u];
+        }
+      }
+      acc[c] = t;
+    }
+  }
+  float* out = partial + blockIdx.z * job_stride + ((int64_t)blockIdx.y * rows + r) * (kRrMaxC + 1);
+#pragma unroll
+  for (int c = 0; c <= kRrMaxC; ++c) out[c] = acc[c];
+}
+
+__global__ void rr_multi_sum_kernel(RrJobs jobs, const float* __restrict__ partial, int64_t job_stride, int nchunks) {
+  const RrJob& jb = jobs.job[blockIdx.y];
+  const int rows = jb.A ? jb.rows : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = (int)(t / (kRrMaxC + 1)), c = (int)(t % (kRrMaxC + 1));
+  if (r >= rows || (c >= jb.C && c != kRrMaxC)) return;
+  const float* p = partial + blockIdx.y * job_stride;
+  float s = 0.f;
+#pragma unroll 8
+  for (int k = 0; k < nchunks; ++k) s += p[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
+  if (c == kRrMaxC) {
+    if (jb.bias) jb.bias[r] = s;
+  } else if (jb.out) {
+    jb.out[(int64_t)r * jb.C + c] = s;
+  }
+}
+
+int64_t rr_multi_job_floats(int rows, int64_t B) { return (int64_t)rr_chunks(B) * rows * (kRrMaxC + 1); }
+
+hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B, int64_t ldv, float* partial,
+                                   hipStream_t s) {
+  if (jobs.n < 1 || jobs.n > kRrMaxJobs || B <= 0) return hipErrorInvalidValue;
+  int rmax = 1;
+  for (int j = 0; j < jobs.n; ++j) {
+    const RrJob& jb = jobs.job[j];
+    if (jb.C > kRrMaxC || (jb.C > 0 && !jb.V) || (jb.A && jb.rows <= 0) || (!jb.A && jb.C < 1)) return hipErrorInvalidValue;
+    if (jb.A && jb.rows > rmax) rmax = jb.rows;
+  }
+  const int nch = rr_chunks(B);
+  const int64_t stride = rr_multi_job_floats(rmax, B);
+  const dim3 grid((unsigned)((rmax + 255) / 256), (unsigned)nch, (unsigned)jobs.n);
+  if (a_is_bf16)
+    hipLaunchKernelGGL(rr_multi_partial_kernel<true>, grid, dim3(256), 0, s, jobs, B, ldv, partial, stride);
+  else
+    hipLaunchKernelGGL(rr_multi_partial_kernel<false>, grid, dim3(256), 0, s, jobs, B, ldv, partial, stride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)rmax * (kRrMaxC + 1);
+  hipLaunchKernelGGL(rr_multi_sum_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)jobs.n), dim3(256), 0, s, jobs,
+                     partial, stride, nch);
   return hipGetLastError();
 }
 

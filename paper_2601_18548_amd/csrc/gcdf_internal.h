@@ -88,6 +88,23 @@ hipError_t pack_input_layer(const float* W1, const float* b1, float* w1p, int wi
 // Reorder nvec consecutive row vectors of length width into lane-major row order.
 hipError_t pack_row_vectors(const float* src, float* dst, int width, int nvec, hipStream_t s);
 
+// Every packed array of a network (pack_matrix of W2..W4 and their transposes,
+// pack_row_vectors of b2, b3, b4 and w_out, pack_input_layer) in one launch.
+struct PackJob {
+  int width, mode, in_dim;
+  const float* W1;     // [width][in_dim]
+  const float* b1;     // [width]
+  const float* Wl[3];  // W2, W3, W4 (row-major, width x width)
+  const float* bl[3];  // b2, b3, b4
+  const float* w5;     // w_out [width]
+  void* fwd[3];        // packed W2..W4
+  void* bwd[3];        // packed W2^T..W4^T
+  float* bh;           // [3][width] lane-major
+  float* w5p;          // [width] lane-major
+  float* w1p;          // [width][12]
+};
+hipError_t pack_network(const PackJob& pj, hipStream_t s);
+
 // Obstacle partitions: offsets[i+1] - offsets[i] = number of points within `radius`
 // (planar distance) of reference base position i (ref + i * ref_stride), offsets[0] = 0.
 // spheres: points hold (x, y, z, s) and the limit is radius + s.
@@ -211,6 +228,27 @@ int wgrad_chunks(int64_t B);
 int rr_chunks(int64_t B);
 hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
                              float* out, float* bias, float* partial, hipStream_t s, bool accumulate = false);
+// Up to kRrMaxJobs such reductions over one batch in one pass (two launches):
+// job j reduces A (rows x batch, blocked layout; NULL: a single row of ones)
+// against V (C <= 9 rows of stride ldv, shared ldv) into out (rows x C) and bias
+// (rows), either NULL; no job accumulates onto another's outputs.  partial needs
+// n * rr_multi_job_floats(max rows, B) floats.
+constexpr int kRrMaxJobs = 6;
+struct RrJob {
+  const void* A;
+  int rows;
+  const float* V;
+  int C;
+  float* out;
+  float* bias;
+};
+struct RrJobs {
+  RrJob job[kRrMaxJobs];
+  int n;
+};
+int64_t rr_multi_job_floats(int rows, int64_t B);
+hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B, int64_t ldv, float* partial,
+                                   hipStream_t s);
 // *out = sum_{i < n} x[i] in a fixed order (one workgroup).
 hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s);
 

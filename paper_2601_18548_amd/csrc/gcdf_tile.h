@@ -488,7 +488,10 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 // the blocked feature-major layout: element (f, i) of a [W x batch] array sits at
 // ((i / S) * W + f) * S + i % S with S = 16 bytes of samples (8 BF16 or 4 FP32),
 // so the 16-byte fragments of consecutive features are adjacent.  Zeros for the
-// ragged tail of the tile.  All threads take part.
+// ragged tail of the tile.  All threads take part.  (The stores go through the
+// caches on purpose: the weight-gradient kernels that follow read the dumps back,
+// largely from the last-level cache; non-temporal stores made the backward pass
+// half again as slow.)
 // ----------------------------------------------------------------------------
 template <int W, int MODE>
 __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {

@@ -74,16 +74,23 @@ struct DevGuard {
 hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
   const Offsets o(tr->W);
   char* base = static_cast<char*>(tr->wbuf);
-  hipError_t e = gcdf::pack_input_layer(params + o.W1, params + o.b1, const_cast<float*>(tr->net.w1p), tr->W,
-                                        gcdf::kInDim, s);
-  for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::pack_row_vectors(params + o.bl[l], const_cast<float*>(tr->net.bh) + (size_t)l * tr->W, tr->W, 1, s);
-  if (e == hipSuccess) e = gcdf::pack_row_vectors(params + o.w5, const_cast<float*>(tr->net.w5), tr->W, 1, s);
-  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
-    e = gcdf::pack_matrix(params + o.Wl[l], base + tr->off_m + (size_t)l * tr->mbytes, tr->W, tr->mode, false, s);
-    if (e == hipSuccess)
-      e = gcdf::pack_matrix(params + o.Wl[l], base + tr->off_m + (size_t)(3 + l) * tr->mbytes, tr->W, tr->mode, true, s);
+  gcdf::PackJob pj{};
+  pj.width = tr->W;
+  pj.mode = tr->mode;
+  pj.in_dim = gcdf::kInDim;
+  pj.W1 = params + o.W1;
+  pj.b1 = params + o.b1;
+  for (int l = 0; l < 3; ++l) {
+    pj.Wl[l] = params + o.Wl[l];
+    pj.bl[l] = params + o.bl[l];
+    pj.fwd[l] = base + tr->off_m + (size_t)l * tr->mbytes;
+    pj.bwd[l] = base + tr->off_m + (size_t)(3 + l) * tr->mbytes;
   }
+  pj.w5 = params + o.w5;
+  pj.bh = const_cast<float*>(tr->net.bh);
+  pj.w5p = const_cast<float*>(tr->net.w5);
+  pj.w1p = const_cast<float*>(tr->net.w1p);
+  hipError_t e = gcdf::pack_network(pj, s);
   tr->net.b5p = params + o.b5;
   tr->packed_from = e == hipSuccess ? params : nullptr;
   return e;
@@ -131,8 +138,9 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(&tr->dumpH, dump);
   if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
-  const size_t part = std::max((size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
-                                (size_t)gcdf::rr_chunks(max_batch) * W * 10);
+  const size_t part = std::max({(size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
+                                 (size_t)gcdf::rr_chunks(max_batch) * W * 10,
+                                 (size_t)gcdf::kRrMaxJobs * gcdf::rr_multi_job_floats(W, max_batch)});
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->partial), part * 4);
   if (e != hipSuccess) {
     gcdf_trainer_destroy(tr);
@@ -222,16 +230,18 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
     wj.out[l] = grad + o.Wl[l];
   }
   if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
-  // input layer: dW1 = G_1 V^T, db1 = sum G_1 (the partial buffer is free again:
-  // each reduction follows the previous one on the stream)
-  float* part = tr->partial;
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(G(0), bf, W, B, tr->dumpV, tr->ldb, 9, grad + o.W1, grad + o.b1, part, s);
-  for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::launch_row_reduce(G(l + 1), bf, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], part, s);
-  // output layer: dw_out = H_4 seed, db_out = sum seed
-  if (e == hipSuccess) e = gcdf::launch_row_reduce(H(3), bf, W, B, grad_d, 0, 1, grad + o.w5, nullptr, part, s);
-  if (e == hipSuccess) e = gcdf::launch_vec_sum(grad_d, B, grad + o.b5, s);
+  // One pass over the batch for the rest (the partial buffer is free again: this
+  // follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
+  // db1 = sum G_1; db_l = sum G_l; output layer dw_out = H_4 seed, db_out = sum seed.
+  // (The seed is a single row of V, so the row stride ldb shared with dumpV does not
+  // matter for it.)
+  gcdf::RrJobs rj{};
+  rj.n = 6;
+  rj.job[0] = {G(0), W, tr->dumpV, 9, grad + o.W1, grad + o.b1};
+  for (int l = 0; l < 3; ++l) rj.job[1 + l] = {G(l + 1), W, nullptr, 0, nullptr, grad + o.bl[l]};
+  rj.job[4] = {H(3), W, grad_d, 1, grad + o.w5, nullptr};
+  rj.job[5] = {nullptr, 1, grad_d, 1, grad + o.b5, nullptr};
+  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, bf, B, tr->ldb, tr->partial, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
 }
 

@@ -6,9 +6,9 @@ Tolerances (derivations in the design notes):
             precision form), with the measured error printed
   BF16X2_F16 : the same bar (forward as BF16X2, reverse sweep in FP16: rounding
             emulation predicts relative J errors of a few 1e-3)
-  BF16    : the fast mode does not meet that bar; it is checked against the
-            looser bound that the rounding analysis predicts (|dd| <= 0.25,
-            relative J <= 0.25) so that gross errors still fail.
+  BF16    : the fast mode does not meet that bar; it is checked against about
+            twice its measured maxima (|dd| 3.4e-2, relative J 3.9e-2 over these
+            cases): |dd| <= 0.07, relative J <= 0.08.
 Relative J error per pair is |J - J_ref| / max(|J_ref|, 1e-3 * median |J_ref|).
 """
 import numpy as np
@@ -19,7 +19,7 @@ from paper_2601_18548_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16x2_f16": (1e-3, 1e-2), "bf16": (0.25, 0.25)}
+TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16x2_f16": (1e-3, 1e-2), "bf16": (0.07, 0.08)}
 
 
 @pytest.fixture(scope="module")
@@ -276,3 +276,24 @@ def test_fp16_reverse_overflow_is_reported(gcdf):
     torch.cuda.synchronize()
     ctx.close()
     ref.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16x2_f16", "bf16x2"])
+def test_off_grid_hidden_weights_error_measured(gcdf, oracle_mod, precision):
+    """A network whose hidden weights are FP32 values off the BF16 grid (as FP32
+    master weights of a trainer are): the BF16 precisions multiply the BF16-rounded
+    hidden matrices, so against the FP64 oracle of the FP32 network they carry the
+    rounding of the weights (~2^-9 relative each).  Measured and printed at W=512 on
+    the benchmark point distribution, bounded by 0.1 (value and relative J) so a gross
+    error still fails; with weights on the grid the same cases are under the 1e-3 /
+    1e-2 bar (test_small_workload_matches_oracle)."""
+    w = wl.weights(512, seed=3, bf16_hidden=False)
+    k = wl.knots(16, 41)
+    p = wl.points_patches(400, 42)
+    print("case off-grid weights: width 512 %s K=16 Np=400" % precision, flush=True)
+    _, _, _, d, J = run_eval_grad(gcdf, w, precision, k, p)
+    dr, Jr = oracle_mod.eval_grad(w.to_blob(), k, p)
+    dd, rj = np.abs(d - dr), rel_j_err(J, Jr)
+    report("off-grid weights w512 %s" % precision, dd, rj)
+    assert np.all(np.isfinite(d)) and np.all(np.isfinite(J))
+    assert dd.max() <= 0.1 and rj.max() <= 0.1

@@ -4,7 +4,7 @@ point path, through the C ABI (needs an MI355X).
 
 Tolerances as for point obstacles (the arithmetic differs only by one more
 input-layer product per row): FP32 |dd| <= 5e-5, relative J <= 5e-5; BF16X2
-|dd| <= 1e-3, relative J <= 1e-2; BF16 the loose gross-error bound 0.25.
+|dd| <= 1e-3, relative J <= 1e-2; BF16 about twice its measured maxima (0.07, 0.08).
 """
 import time
 
@@ -16,7 +16,7 @@ from paper_2601_18548_amd import workloads as wl
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16x2_f16": (1e-3, 1e-2), "bf16": (0.25, 0.25)}
+TOL = {"fp32": (5e-5, 5e-5), "bf16x2": (1e-3, 1e-2), "bf16x2_f16": (1e-3, 1e-2), "bf16": (0.07, 0.08)}
 GiB = 1 << 30
 
 
