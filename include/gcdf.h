@@ -322,6 +322,19 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
                                 int64_t B, const float* grad_d, float* grad_params, int32_t reuse_packed,
                                 void* stream);
 
+/* Training with the mean squared error fused in: L = (1/B) sum_i (d_i - y_i)^2
+ * over the samples (knot i, point i), with d the network distance, and its weight
+ * gradient, from one training-mode pass (no separate forward).  Each 64-sample
+ * tile finishes d before its reverse sweep and seeds the sweep with
+ * dL/dd_i = 2 (d_i - y_i) / B; otherwise as gcdf_train_backward (weights packed
+ * from params at every call, deterministic).  target: device float32[B];
+ * loss: device float32[1]; grad_params: device, overwritten; d: device
+ * float32[B] for the distances, or NULL.  EINVAL: NULL tr, params, knots,
+ * points, target, loss or grad_params, or B outside [1, max_batch].  The
+ * trainer's buffers make concurrent calls on one trainer race. */
+gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* knots, const float* points, int64_t B,
+                           const float* target, float* loss, float* grad_params, float* d, void* stream);
+
 /* The training loss of Table I (Sec. III-C) over the samples (knot i, point i)
  * and its weight gradient.  With F the network distance and J = dF/dq the
  * configuration gradient of the query (chain rule through the base frame):

@@ -73,6 +73,13 @@ struct Job {
   void* dumpG;
   float* dumpV;
   int64_t ldb;
+  // fused MSE loss (training, seed NULL, target set): each tile finishes d before its
+  // reverse sweep and seeds it with dL/dd_i = mse_scale (d_i - target_i), written to
+  // seed_out[i], and writes sq_out[i] = inv_b (d_i - target_i)^2 (i < npairs).
+  const float* target;
+  float* seed_out;
+  float* sq_out;
+  float mse_scale, inv_b;
 };
 
 // Packed fragment bytes for one width x width matrix.
@@ -233,7 +240,7 @@ hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B,
 // against V (C <= 9 rows of stride ldv, shared ldv) into out (rows x C) and bias
 // (rows), either NULL; no job accumulates onto another's outputs.  partial needs
 // n * rr_multi_job_floats(max rows, B) floats.
-constexpr int kRrMaxJobs = 6;
+constexpr int kRrMaxJobs = 7;
 struct RrJob {
   const void* A;
   int rows;

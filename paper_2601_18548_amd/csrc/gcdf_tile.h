@@ -572,6 +572,14 @@ struct TileDump {
   int nvalid;
   size_t layer_elems;  // W * ldb
   size_t elem_bytes;
+  // fused MSE loss (Job::target): per-wave output partial sums, the per-query
+  // records (slot 11 takes the seed), and the loss terms
+  float* dred;
+  float* xin;
+  const float* target;
+  float* seed_out;
+  float* sq_out;
+  float mse_scale, inv_b;
   __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
   __device__ __forceinline__ void* g(int l) const { return static_cast<char*>(G) + l * layer_elems * elem_bytes; }
 };
@@ -637,20 +645,51 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   constexpr bool DEFER = defer_stores<W, MODE, TRAIN>(L == 2);
   if constexpr (!DEFER) __syncthreads();
   if constexpr (TRAIN && L == 2) {
-    // training: the layer-4 activations h4 go through LDS first (for dL/dw_out)
+    // training: the layer-4 activations h4 go through LDS first (for dL/dw_out),
+    // and the output-layer partial sums are taken here, so that a fused loss can
+    // finish d before the reverse sweep
     static_for<MT>([&](auto I) {
       static_for<2>([&](auto GP) {
+        const f32x4 w5r[2] = {*reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP),
+                              *reinterpret_cast<const f32x4*>(b.w5 + 16 * I + 8 * GP + 4)};
         static_for<2>([&](auto NT) {
           float v[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = silu_only(acc[I][NT][8 * GP + q]);
+          for (int q = 0; q < 8; ++q) {
+            v[q] = silu_only(acc[I][NT][8 * GP + q]);
+            dpart[NT] += w5r[q >> 2][q & 3] * v[q];
+          }
           act_store_pair<W, MODE, I, GP, NT>(ln, v);
         });
       });
     });
+    if (td.target) {
+      // d over the rows: lane halves, then waves in order, as at the end of the tile
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const float dp = dpart[nt] + __shfl_xor(dpart[nt], 32);
+        if (ln.h == 0) td.dred[ln.wave * kTileQ + 32 * nt + ln.n0] = dp;
+      }
+    }
     __syncthreads();
+    if (td.target && threadIdx.x < kTileQ) {
+      const int n = threadIdx.x;
+      float sum = td.dred[n];
+#pragma unroll
+      for (int w = 1; w < Geo<W, MODE>::NW; ++w) sum += td.dred[w * kTileQ + n];
+      const float dv = sum + *net.b5p;
+      const bool valid = n < td.nvalid;
+      const int64_t q = td.q0 + n;
+      const float r = valid ? dv - td.target[q] : 0.f;
+      const float seed = td.mse_scale * r;  // dL/dd for L = mean (d - target)^2
+      td.xin[n * Geo<W, MODE>::XIN_FLOATS + 11] = seed;
+      if (valid) {
+        td.seed_out[q] = seed;
+        td.sq_out[q] = td.inv_b * (r * r);
+      }
+    }
     dump_tile<W, MODE>(td.act, td.h(3), td.ldb, td.q0, td.nvalid);
-    __syncthreads();  // h4 fully read before g4 overwrites the tile
+    __syncthreads();  // h4 fully read before g4 overwrites the tile; seeds written
   }
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
@@ -671,7 +710,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
             sp[L][I][NT][j] = park(dv);
             v[q] = hv;
           } else {
-            dpart[NT] += w5r[q >> 2][q & 3] * hv;
+            if constexpr (!TRAIN) dpart[NT] += w5r[q >> 2][q & 3] * hv;  // (training: summed above)
             v[q] = seed * (w5r[q >> 2][q & 3] * dv);  // g4 = seed * w5 * SiLU'(z4)
           }
         }
@@ -992,6 +1031,16 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.nvalid = (int)(qlimit - q0 < kTileQ ? qlimit - q0 : kTileQ);
     td.layer_elems = (size_t)W * job.ldb;
     td.elem_bytes = MODE == kFP32 ? 4 : 2;
+    // the fused loss's partial sums: the idle half of a pure-BF16 tile, or the
+    // reduction buffer when it has its own space
+    static_assert(!G::RED_IN_ACT || MODE == kBF16, "training tile layout");
+    td.dred = G::RED_IN_ACT ? reinterpret_cast<float*>(tc.act + G::ACT_BYTES / 2) : red;
+    td.xin = xin;
+    td.target = job.seed ? nullptr : job.target;
+    td.seed_out = job.seed_out;
+    td.sq_out = job.sq_out;
+    td.mse_scale = job.mse_scale;
+    td.inv_b = job.inv_b;
   }
   fwd_input<W, MODE, PAIRS, SPH>(ln, b);
   __syncthreads();

@@ -7,7 +7,10 @@
 //           g_l = dL/dz_l written in a blocked feature-major layout -- then
 //             dW_l = G_l H_{l-1}^T       (matrix cores, split-K, fixed-order sum),
 //             dW_1 = G_1 V^T, db_l = sum_i G_l, dw_out = H_4 seed, db_out = sum seed
-//           (fixed-order row reductions).
+//           (fixed-order row reductions);
+// mse     : the backward's launches with the loss L = mean_i (d_i - y_i)^2 fused in:
+//           each tile finishes d before its reverse sweep and seeds it with
+//           dL/dd_i = 2 (d_i - y_i) / B, so no separate forward runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +32,7 @@ struct gcdf_trainer {
   void* dumpH = nullptr;
   void* dumpG = nullptr;
   float* dumpV = nullptr;
+  float* mse = nullptr;  // fused MSE: per-sample seeds [ldb], then loss terms [ldb]
   float* partial = nullptr;
   const float* packed_from = nullptr;  // params pointer of the last packing
   // Table I loss workspace (allocated at its first use)
@@ -103,6 +107,58 @@ gcdf_status check(const gcdf_trainer* tr, const float* params, const float* knot
   return GCDF_OK;
 }
 
+// The training-mode query over the batch as a pair list (sample i = knot i, point i).
+gcdf::Job training_job(const gcdf_trainer* tr, const float* knots, const float* points, int64_t B) {
+  gcdf::Job job{};
+  job.knots = knots;
+  job.points = points;
+  job.K = B;
+  job.Np = B;
+  job.npairs = B;
+  job.dumpH = tr->dumpH;
+  job.dumpG = tr->dumpG;
+  job.dumpV = tr->dumpV;
+  job.ldb = tr->ldb;
+  return job;
+}
+
+// After the training-mode query: the weight gradients from its dumps and the
+// per-sample seeds dL/dd; with sq set, also *loss = sum_i sq[i].
+hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, const float* sq, float* loss, float* grad,
+                            hipStream_t s) {
+  const int W = tr->W;
+  const Offsets o(W);
+  const size_t esz = tr->mode == GCDF_FP32 ? 4 : 2;
+  const size_t layer = (size_t)W * tr->ldb * esz;
+  auto H = [&](int l) { return static_cast<const char*>(tr->dumpH) + l * layer; };
+  auto G = [&](int l) { return static_cast<const char*>(tr->dumpG) + l * layer; };
+  const bool bf = tr->mode != GCDF_FP32;
+  const int nch = gcdf::wgrad_chunks(B);
+  const int gmode = bf ? gcdf::kBF16 : gcdf::kFP32;
+  // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4, one launch
+  gcdf::WgradJobs wj{};
+  wj.n = 3;
+  for (int l = 0; l < 3; ++l) {
+    wj.G[l] = G(l + 1);
+    wj.H[l] = H(l);
+    wj.out[l] = grad + o.Wl[l];
+  }
+  hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
+  // One pass over the batch for the rest (the partial buffer is free again: this
+  // follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
+  // db1 = sum G_1; db_l = sum G_l; output layer dw_out = H_4 seed, db_out = sum seed;
+  // the loss.  (Single-row V operands ignore the shared row stride ldb.)
+  gcdf::RrJobs rj{};
+  rj.n = sq ? 7 : 6;
+  rj.job[0] = {G(0), W, tr->dumpV, 9, grad + o.W1, grad + o.b1};
+  for (int l = 0; l < 3; ++l) rj.job[1 + l] = {G(l + 1), W, nullptr, 0, nullptr, grad + o.bl[l]};
+  rj.job[4] = {H(3), W, seed, 1, grad + o.w5, nullptr};
+  rj.job[5] = {nullptr, 1, seed, 1, grad + o.b5, nullptr};
+  if (sq) rj.job[6] = {nullptr, 1, sq, 1, loss, nullptr};
+  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, bf, B, tr->ldb, tr->partial, s);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -138,6 +194,7 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(&tr->dumpH, dump);
   if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->mse), (size_t)2 * tr->ldb * 4);
   const size_t part = std::max({(size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
                                  (size_t)gcdf::rr_chunks(max_batch) * W * 10,
                                  (size_t)gcdf::kRrMaxJobs * gcdf::rr_multi_job_floats(W, max_batch)});
@@ -168,6 +225,7 @@ void gcdf_trainer_destroy(gcdf_trainer* tr) {
   (void)hipFree(tr->dumpH);
   (void)hipFree(tr->dumpG);
   (void)hipFree(tr->dumpV);
+  (void)hipFree(tr->mse);
   (void)hipFree(tr->partial);
   (void)hipFree(tr->t1);
   delete tr;
@@ -199,50 +257,34 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
   if (!grad_d || !grad) return tfail(GCDF_EINVAL, "grad_d or grad_params is NULL");
   DevGuard g(tr->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int W = tr->W;
-  const Offsets o(W);
-  const size_t esz = tr->mode == GCDF_FP32 ? 4 : 2;
-  const size_t layer = (size_t)W * tr->ldb * esz;
-  auto H = [&](int l) { return static_cast<const char*>(tr->dumpH) + l * layer; };
-  auto G = [&](int l) { return static_cast<const char*>(tr->dumpG) + l * layer; };
-  const bool bf = tr->mode != GCDF_FP32;
   hipError_t e = (reuse_packed && tr->packed_from == params) ? hipSuccess : pack(tr, params, s);
-  gcdf::Job job{};
-  job.knots = knots;
-  job.points = points;
-  job.K = B;
-  job.Np = B;
-  job.npairs = B;
+  gcdf::Job job = training_job(tr, knots, points, B);
   job.seed = grad_d;
-  job.dumpH = tr->dumpH;
-  job.dumpG = tr->dumpG;
-  job.dumpV = tr->dumpV;
-  job.ldb = tr->ldb;
   if (e == hipSuccess) e = gcdf::launch_fused(tr->net, job, true, true, tr->num_cu, s);
-  const int nch = gcdf::wgrad_chunks(B);
-  const int gmode = bf ? gcdf::kBF16 : gcdf::kFP32;
-  // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4, one launch
-  gcdf::WgradJobs wj{};
-  wj.n = 3;
-  for (int l = 0; l < 3; ++l) {
-    wj.G[l] = G(l + 1);
-    wj.H[l] = H(l);
-    wj.out[l] = grad + o.Wl[l];
-  }
-  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
-  // One pass over the batch for the rest (the partial buffer is free again: this
-  // follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
-  // db1 = sum G_1; db_l = sum G_l; output layer dw_out = H_4 seed, db_out = sum seed.
-  // (The seed is a single row of V, so the row stride ldb shared with dumpV does not
-  // matter for it.)
-  gcdf::RrJobs rj{};
-  rj.n = 6;
-  rj.job[0] = {G(0), W, tr->dumpV, 9, grad + o.W1, grad + o.b1};
-  for (int l = 0; l < 3; ++l) rj.job[1 + l] = {G(l + 1), W, nullptr, 0, nullptr, grad + o.bl[l]};
-  rj.job[4] = {H(3), W, grad_d, 1, grad + o.w5, nullptr};
-  rj.job[5] = {nullptr, 1, grad_d, 1, grad + o.b5, nullptr};
-  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, bf, B, tr->ldb, tr->partial, s);
+  if (e == hipSuccess) e = weight_gradients(tr, B, grad_d, nullptr, nullptr, grad, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_backward: %s", hipGetErrorString(e));
+}
+
+gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* knots, const float* points, int64_t B,
+                           const float* target, float* loss, float* grad, float* d, void* stream) {
+  gcdf_status st = check(tr, params, knots, points, B);
+  if (st != GCDF_OK) return st;
+  if (!target || !loss || !grad) return tfail(GCDF_EINVAL, "target, loss or grad_params is NULL");
+  DevGuard g(tr->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pack(tr, params, s);
+  gcdf::Job job = training_job(tr, knots, points, B);
+  float* seed = tr->mse;
+  float* sq = tr->mse + tr->ldb;
+  job.target = target;
+  job.seed_out = seed;
+  job.sq_out = sq;
+  job.mse_scale = (float)(2.0 / (double)B);
+  job.inv_b = (float)(1.0 / (double)B);
+  job.d = d;
+  if (e == hipSuccess) e = gcdf::launch_fused(tr->net, job, true, true, tr->num_cu, s);
+  if (e == hipSuccess) e = weight_gradients(tr, B, seed, sq, loss, grad, s);
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_mse: %s", hipGetErrorString(e));
 }
 
 gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float* knots, const float* points,

@@ -80,6 +80,22 @@ class Trainer:
         return grad
 
 
+    def mse(self, params, knots, points, target, grad=None, d=None, stream=None):
+        """Mean squared error of the network distances against target and its weight
+        gradient in one pass (gcdf_train_mse): (loss float32[1], grad)."""
+        import torch
+
+        B = knots.shape[0]
+        if grad is None:
+            grad = torch.empty_like(params)
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        self._packed = None
+        _check(library().gcdf_train_mse(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
+                                        target.data_ptr(), loss.data_ptr(), grad.data_ptr(),
+                                        d.data_ptr() if d is not None else None, _stream(stream)))
+        self._packed = (params, params._version)
+        return loss, grad
+
     LAMBDA_PAPER = (5.0, 0.1, 0.01, 0.01)  # loss weights of Sec. V-A
 
     def table1(self, params, knots, points, fstar, Jstar, m_diag, lam=LAMBDA_PAPER, grad=None, stream=None):
@@ -108,6 +124,19 @@ def _checked(t, dtype_name):
     return t
 
 
+def _check_samples(params, knots, points, trainer):
+    _checked(params, "params")
+    _checked(knots, "knots")
+    _checked(points, "points")
+    B = knots.shape[0]
+    if knots.dim() != 2 or knots.shape[1] != 9 or tuple(points.shape) != (B, 3):
+        raise ValueError("knots must be (B, 9) and points (B, 3)")
+    if params.numel() != param_count(trainer.width):
+        raise ValueError("params must hold %d floats" % param_count(trainer.width))
+    if B > trainer.max_batch:
+        raise ValueError("batch %d exceeds the trainer's max_batch %d" % (B, trainer.max_batch))
+
+
 def _make_function():
     import torch
 
@@ -116,16 +145,7 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, params, knots, points, trainer):
-            _checked(params, "params")
-            _checked(knots, "knots")
-            _checked(points, "points")
-            B = knots.shape[0]
-            if knots.dim() != 2 or knots.shape[1] != 9 or tuple(points.shape) != (B, 3):
-                raise ValueError("knots must be (B, 9) and points (B, 3)")
-            if params.numel() != param_count(trainer.width):
-                raise ValueError("params must hold %d floats" % param_count(trainer.width))
-            if B > trainer.max_batch:
-                raise ValueError("batch %d exceeds the trainer's max_batch %d" % (B, trainer.max_batch))
+            _check_samples(params, knots, points, trainer)
             d = trainer.forward(params, knots, points)
             ctx.save_for_backward(params, knots, points)
             ctx.trainer = trainer
@@ -141,18 +161,48 @@ def _make_function():
             ctx.params = None
             return g, None, None, None
 
-    return GcdfNet
+    class GcdfMSE(torch.autograd.Function):
+        """loss = mean (network(params)(samples) - target)^2; the forward computes the
+        weight gradient with it (one training-mode pass), the backward scales it."""
+
+        @staticmethod
+        def forward(ctx, params, knots, points, target, trainer):
+            _check_samples(params, knots, points, trainer)
+            _checked(target, "target")
+            if tuple(target.shape) != (knots.shape[0],):
+                raise ValueError("target must be (B,)")
+            loss, g = trainer.mse(params.detach(), knots, points, target)
+            ctx.grad = g
+            return loss.reshape(())
+
+        @staticmethod
+        def backward(ctx, grad_loss):
+            g = ctx.grad.mul_(grad_loss)
+            ctx.grad = None
+            return g, None, None, None, None
+
+    return GcdfNet, GcdfMSE
 
 
 _fn = None
 
 
-def gcdf_net(params, knots, points, trainer):
-    """Differentiable network distances of the samples (knot i, point i)."""
+def _functions():
     global _fn
     if _fn is None:
         _fn = _make_function()
-    return _fn.apply(params, knots, points, trainer)
+    return _fn
+
+
+def gcdf_net(params, knots, points, trainer):
+    """Differentiable network distances of the samples (knot i, point i)."""
+    return _functions()[0].apply(params, knots, points, trainer)
+
+
+def gcdf_mse(params, knots, points, target, trainer):
+    """Differentiable mean squared error of the network distances of the samples
+    (knot i, point i) against target, loss and weight gradient from one fused pass."""
+    return _functions()[1].apply(params, knots, points, target, trainer)
 
 
 class Adam:
@@ -198,10 +248,10 @@ def adam(params, lr: float = 5e-3, betas=(0.9, 0.999)):
 
 
 def mse_step(params, opt, trainer, knots, points, targets):
-    """One training step: MSE loss through the HIP network, backward, optimiser step."""
-    opt.zero_grad(set_to_none=False)
-    d = gcdf_net(params, knots, points, trainer)
-    loss = ((d - targets) ** 2).mean()
+    """One training step: the fused MSE loss through the HIP network, backward,
+    optimiser step."""
+    opt.zero_grad(set_to_none=True)
+    loss = gcdf_mse(params, knots, points, targets, trainer)
     loss.backward()
     opt.step()
     return loss

@@ -87,6 +87,74 @@ def test_weight_gradients_match_oracle_multi_chunk(tr_mod, oracle_mod, precision
         assert err <= tol, name
 
 
+def fused_grads(tr_mod, precision, w, k, p, y):
+    trainer = tr_mod.Trainer(256, precision, max_batch=len(k))
+    params = tr_mod.flat_params(w)
+    kt, pt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda()
+    d = torch.empty(len(k), device="cuda")
+    loss, g = trainer.mse(params, kt, pt, torch.from_numpy(y).cuda(), d=d)
+    torch.cuda.synchronize()
+    return trainer, params, kt, pt, float(loss.item()), d.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("B", [300, MULTI_B])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_fused_mse_matches_oracle(tr_mod, oracle_mod, precision, tol, B):
+    """gcdf_train_mse: the loss, the distances and the weight gradient of one fused
+    pass against the oracle's (d is finished inside each tile before its reverse
+    sweep, which the seeds 2 (d_i - y_i) / B come from)."""
+    w = wl.weights(256, seed=40, bf16_hidden=False)
+    k, p, y = batch(B, 15)
+    print("case fused MSE B=%d %s" % (B, precision), flush=True)
+    _, _, _, _, loss, d, g = fused_grads(tr_mod, precision, w, k, p, y)
+    loss_ref, gref = oracle_mod.mse_grad(w.to_blob(), k.astype(np.float64), p.astype(np.float64), y)
+    if precision == "fp32":
+        dref, _ = oracle_mod.eval_pairs(w.to_blob(), k, p, np.arange(B), np.arange(B), with_grad=False)
+        assert np.abs(d - dref).max() <= 1e-5
+    lerr = abs(loss - loss_ref) / loss_ref
+    print("%s B=%d loss %.6f ref %.6f rel err %.2e" % (precision, B, loss, loss_ref, lerr), flush=True)
+    assert lerr <= (1e-5 if precision == "fp32" else 2e-2)
+    for name, a, b in zip(NAMES, split(g, w), gref):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("%s B=%d fused %-5s rel err %.2e" % (precision, B, name, err), flush=True)
+        assert np.all(np.isfinite(a))
+        assert err <= tol, name
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_fused_mse_agrees_with_forward_then_backward(tr_mod, precision, tol):
+    """The fused pass against the separate forward + backward with torch's MSE seeds:
+    the same distances, the loss of those distances, nearly the same gradient (the
+    seeds round differently)."""
+    w = wl.weights(256, seed=41, bf16_hidden=False)
+    k, p, y = batch(MULTI_B, 16)
+    _, _, _, _, d0, g0 = gpu_grads(tr_mod, precision, w, k, p, y)
+    trainer, _, _, _, loss, d, g = fused_grads(tr_mod, precision, w, k, p, y)
+    assert np.abs(d - d0).max() <= 1e-6 * max(1.0, np.abs(d0).max())
+    ref = float(np.mean((d0.astype(np.float64) - y) ** 2))
+    assert abs(loss - ref) <= 1e-5 * ref
+    err = np.linalg.norm(g - g0) / np.linalg.norm(g0)
+    print("%s fused vs separate gradient rel diff %.2e" % (precision, err), flush=True)
+    assert err <= tol
+    trainer.close()
+
+
+def test_fused_mse_autograd_and_determinism(tr_mod):
+    w = wl.weights(256, seed=42, bf16_hidden=False)
+    k, p, y = batch(2048 + 37, 17)
+    trainer, params, kt, pt, loss, d, g = fused_grads(tr_mod, "bf16", w, k, p, y)
+    yt = torch.from_numpy(y).cuda()
+    _, g2 = trainer.mse(params, kt, pt, yt)
+    assert np.array_equal(g, g2.cpu().numpy())  # deterministic
+    pr = params.clone().requires_grad_(True)
+    lt = tr_mod.gcdf_mse(pr, kt, pt, yt, trainer)
+    assert lt.dim() == 0 and float(lt.item()) == loss
+    (3.0 * lt).backward()  # the upstream gradient scales the fused one
+    assert torch.equal(pr.grad, 3.0 * torch.from_numpy(g).cuda())
+    with pytest.raises(ValueError):
+        tr_mod.gcdf_mse(pr, kt, pt, yt[:-1].contiguous(), trainer)
+
+
 def test_gradient_matches_finite_differences_multi_chunk(tr_mod):
     """Central differences of the GPU's own FP32 MSE loss at the multi-chunk batch."""
     w = wl.weights(256, seed=39, bf16_hidden=False)
