@@ -102,7 +102,7 @@ __global__ __launch_bounds__((Geo<W, kFP32>::THREADS), 1) void table1_tiles(cons
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t q0 = tile * kTileQ;
     const int nvalid = (int)(job.B - q0 < kTileQ ? job.B - q0 : kTileQ);
-    auto dumpl = [&](float* arrbase, int l) { dump_tile<W, MODE>(tc.act, arrbase + l * layer, job.ldb, q0, nvalid); };
+    auto dumpl = [&](float* arrbase, int l) { dump_tile<W, MODE>(tc.act, nullptr, arrbase + l * layer, job.ldb, q0, nvalid); };
     // ---- prologue: base-frame points, fbar and u of the tile's samples ----
     if (tid < kTileQ) {
       const int64_t q = q0 + tid;
@@ -992,6 +992,30 @@ hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B
 
 hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s) {
   hipLaunchKernelGGL(vec_sum_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+// Entry (r, f) = sum over workgroups w of part[(r W + f) nparts + w]: one wave
+// per entry, lane l adding workgroups l, l + 64, ... in order, then the 64 lane
+// sums in a fixed butterfly (the result does not depend on scheduling).
+__global__ void part_sum_kernel(const float* __restrict__ part, int nparts, int W, PartOut out) {
+  const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= kTrainSumRows * W) return;
+  const int r = j / W, f = j % W;
+  if (!out.base[r] || f >= out.n[r]) return;
+  const float* p = part + (int64_t)j * nparts;
+  float s = 0.f;
+  for (int w = lane; w < nparts; w += 64) s += p[w];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out.base[r][(int64_t)f * out.stride[r]] = s;
+}
+
+hipError_t launch_part_sum(const float* part, int nparts, int width, const PartOut& out, hipStream_t s) {
+  if (nparts < 1 || width < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(part_sum_kernel, dim3((unsigned)((kTrainSumRows * width + 3) / 4)), dim3(256), 0, s, part, nparts,
+                     width, out);
   return hipGetLastError();
 }
 

@@ -75,12 +75,18 @@ struct Job {
   int64_t ldb;
   // fused MSE loss (training, seed NULL, target set): each tile finishes d before its
   // reverse sweep and seeds it with dL/dd_i = mse_scale (d_i - target_i), written to
-  // seed_out[i], and writes sq_out[i] = inv_b (d_i - target_i)^2 (i < npairs).
+  // seed_out[i], and writes sq_out[i] = inv_b (d_i - target_i)^2 (i < npairs; both
+  // nullable).
   const float* target;
   float* seed_out;
   float* sq_out;
   float mse_scale, inv_b;
+  // training, pure BF16: per-workgroup sums [kTrainSumRows][W][grid] (rows:
+  // sum_i g_l for l = 1..4; sum_i seed_i h4_i; sum_i g1_i v_c(i) for the nine
+  // inputs c; sum_i seed_i; the fused loss), so that h4 and g1 are not written
+  float* bias_part;
 };
+constexpr int kTrainSumRows = 16;
 
 // Packed fragment bytes for one width x width matrix.
 size_t packed_matrix_bytes(int width, int mode);
@@ -258,6 +264,19 @@ hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B
                                    hipStream_t s);
 // *out = sum_{i < n} x[i] in a fixed order (one workgroup).
 hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s);
+// Workgroups of a one-shot fused_query launch over ntiles tiles: one per compute
+// unit (each holds one), fewer for small launches.  Training's per-workgroup sums
+// are indexed by it.
+inline int fused_grid(int64_t ntiles, int num_cu) { return (int)(ntiles < num_cu ? ntiles : num_cu); }
+// The training kernel's per-workgroup sums (Job::bias_part, nparts workgroups)
+// added in a fixed order: entry f < n[r] of row r goes to base[r][f * stride[r]]
+// (rows with a NULL base are dropped).
+struct PartOut {
+  float* base[kTrainSumRows];
+  int stride[kTrainSumRows];
+  int n[kTrainSumRows];
+};
+hipError_t launch_part_sum(const float* part, int nparts, int width, const PartOut& out, hipStream_t s);
 
 // Table I training loss (width 256, FP32): per 64-sample tile, the forward, the
 // reverse sweep for e = dF/dv, the tangent pass along u and the reverse mode through

@@ -492,9 +492,28 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 // caches on purpose: the weight-gradient kernels that follow read the dumps back,
 // largely from the last-level cache; non-temporal stores made the backward pass
 // half again as slow.)
+// BF16: the tile is transposed into `stage` (32 KiB of LDS, the idle half of a
+// pure-BF16 tile) and then copied out, so that a wave's store instruction writes
+// 1 KiB of consecutive pieces instead of 16 bytes into each of 64 cache lines.
+// Piece P (16 bytes: 8 samples of one feature) sits at slot P ^ ((P >> 4) & 7),
+// which spreads the 16 pieces written by 16 consecutive lanes over 16 different
+// bank groups, and those read by 16 consecutive lanes too.
+// BF16, with sums: the copy also adds, over the tile's samples i, to LDS rows
+// (per feature f) sum_i x[f][i] w_i (w_i = seed_i, or 1) and optionally
+// sum_i x[f][i] v_c(i) for the nine network inputs v_c, in a fixed order:
+// samples within a piece, pieces in order, then the threads sharing a feature in
+// order.  store false: the sums only, nothing written to HBM.
 // ----------------------------------------------------------------------------
+struct DumpSums {
+  float* row;          // [W]: sum_i x[f][i] w_i
+  const float* seed;   // w_i = seed[i * XIN_FLOATS] (the records' seed slot), or NULL: w_i = 1
+  float* in_rows;      // [9][W]: sum_i x[f][i] v_c(i), or NULL
+  const float* xin;    // per-query records: v = p' (slots 0..2), arm (slots 5..10)
+};
+
 template <int W, int MODE>
-__device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ldb, int64_t q0, int nvalid) {
+__device__ __forceinline__ void dump_tile(const char* act, char* stage, void* dst, int64_t ldb, int64_t q0,
+                                          int nvalid, const DumpSums* sums = nullptr, bool store = true) {
   (void)ldb;
   for (int f = threadIdx.x; f < W && MODE == kFP32; f += Geo<W, MODE>::THREADS) {
     const float* a = reinterpret_cast<const float*>(act);
@@ -513,11 +532,14 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
   if constexpr (MODE != kFP32) {
     // The hi plane holds, for each group of 8 features and each query n, the 8
     // features' values as one 16-byte word.  A thread reads the 8x8 block of 8
-    // consecutive queries, transposes it in registers and writes the 8 features'
-    // 16-byte pieces of that query block.
+    // consecutive queries, transposes it in registers and stages the 8 features'
+    // 16-byte pieces of that query block; then every thread copies pieces out.
+    static_assert(MODE == kBF16 && W * kTileQ * 2 <= Geo<W, MODE>::ACT_BYTES / 2, "staging needs a pure-BF16 tile");
+    static_assert(10 * Geo<W, MODE>::THREADS * 4 <= W * kTileQ * 2, "the sums' combine buffer shares the staging area");
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const char* a = act;
     constexpr int NG = W / 8;  // feature groups
+    constexpr int NP = W * (kTileQ / 8);  // pieces: (query block nb, feature f) at nb W + f
     for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += Geo<W, MODE>::THREADS) {
       const int g8 = t % NG, nb = t / NG;
       const int gbyte = (g8 >> 1) * Geo<W, MODE>::STEP_BYTES + (g8 & 1) * 1024;  // 16-feature step, 8-feature half
@@ -535,8 +557,48 @@ __device__ __forceinline__ void dump_tile(const char* act, void* dst, int64_t ld
           const uint32_t x0 = m[2 * jj][fl >> 1], x1 = m[2 * jj + 1][fl >> 1];
           row[jj] = (fl & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
         }
-        __bf16* o = static_cast<__bf16*>(dst) + (((q0 >> 3) + nb) * W + 8 * g8 + fl) * 8;
-        *reinterpret_cast<u32x4*>(o) = row;
+        const int P = nb * W + 8 * g8 + fl;
+        *reinterpret_cast<u32x4*>(stage + (P ^ ((P >> 4) & 7)) * 16) = row;
+      }
+    }
+    __syncthreads();
+    // the tile's pieces are consecutive in the dump: piece P at element ((q0 / 8) W + P) 8
+    constexpr int T = Geo<W, MODE>::THREADS;
+    static_assert(T % W == 0, "a thread's pieces share one feature");
+    constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
+    __bf16* o = static_cast<__bf16*>(dst) + (q0 >> 3) * W * 8;
+    float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // row, then the 9 inputs
+    for (int P = threadIdx.x; P < NP; P += T) {
+      const u32x4 v = *reinterpret_cast<const u32x4*>(stage + (P ^ ((P >> 4) & 7)) * 16);
+      if (store) *reinterpret_cast<u32x4*>(o + P * 8) = v;
+      if (sums) {
+        const int n0 = (P / W) * 8;  // word w: samples n0 + 2w (low half), n0 + 2w + 1
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t word = v[e >> 1];
+          const float x = __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
+          const float* rec = sums->xin + (n0 + e) * XF;
+          part[0] += sums->seed ? x * sums->seed[(n0 + e) * XF] : x;
+          if (sums->in_rows) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) part[1 + c] += x * rec[c < 3 ? c : c + 2];
+          }
+        }
+      }
+    }
+    if (sums) {
+      const int nv = sums->in_rows ? 10 : 1;
+      float* cb = reinterpret_cast<float*>(stage);
+      __syncthreads();  // every thread has copied its pieces out of the staging area
+      for (int k = 0; k < nv; ++k) cb[k * T + threadIdx.x] = part[k];
+      __syncthreads();
+      if (threadIdx.x < W) {
+        for (int k = 0; k < nv; ++k) {
+          float t = cb[k * T + threadIdx.x];
+#pragma unroll
+          for (int u = 1; u < T / W; ++u) t += cb[k * T + threadIdx.x + u * W];
+          (k == 0 ? sums->row : sums->in_rows + (k - 1) * W)[threadIdx.x] += t;
+        }
       }
     }
   }
@@ -566,6 +628,7 @@ struct Bases {
 // Dump of the current LDS tile for training (no-op when not training).
 struct TileDump {
   const char* act;  // the LDS activation tile
+  char* stage;      // BF16: LDS staging of a dump (the tile's idle half)
   void* H;
   void* G;
   int64_t ldb, q0;
@@ -580,6 +643,14 @@ struct TileDump {
   float* seed_out;
   float* sq_out;
   float mse_scale, inv_b;
+  // per-workgroup sums over its samples (LDS, [kTrainSumRows][width]; NULL when
+  // these gradients are reduced from the dumps instead): rows 0..3 the bias
+  // gradients sum_i g_l (l = 1..4), row 4 dL/dw_out = sum_i seed_i h4_i, rows
+  // 5..13 dW1[:, c] = sum_i g1_i v_c(i), row 14 (first entry) db_out = sum_i seed_i,
+  // row 15 (first entry) the fused loss sum_i (d_i - target_i)^2 / B
+  float* bsum;
+  int width;
+  __device__ __forceinline__ float* row(int r) const { return bsum ? bsum + r * width : nullptr; }
   __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
   __device__ __forceinline__ void* g(int l) const { return static_cast<char*>(G) + l * layer_elems * elem_bytes; }
 };
@@ -672,23 +743,45 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
       }
     }
     __syncthreads();
-    if (td.target && threadIdx.x < kTileQ) {
+    if (threadIdx.x < kTileQ && (td.target || td.bsum)) {  // wave 0, one lane per query
       const int n = threadIdx.x;
-      float sum = td.dred[n];
+      float* seedp = td.xin + n * Geo<W, MODE>::XIN_FLOATS + 11;
+      float sq = 0.f;
+      if (td.target) {
+        float sum = td.dred[n];
 #pragma unroll
-      for (int w = 1; w < Geo<W, MODE>::NW; ++w) sum += td.dred[w * kTileQ + n];
-      const float dv = sum + *net.b5p;
-      const bool valid = n < td.nvalid;
-      const int64_t q = td.q0 + n;
-      const float r = valid ? dv - td.target[q] : 0.f;
-      const float seed = td.mse_scale * r;  // dL/dd for L = mean (d - target)^2
-      td.xin[n * Geo<W, MODE>::XIN_FLOATS + 11] = seed;
-      if (valid) {
-        td.seed_out[q] = seed;
-        td.sq_out[q] = td.inv_b * (r * r);
+        for (int w = 1; w < Geo<W, MODE>::NW; ++w) sum += td.dred[w * kTileQ + n];
+        const float dv = sum + *net.b5p;
+        const bool valid = n < td.nvalid;
+        const int64_t q = td.q0 + n;
+        const float r = valid ? dv - td.target[q] : 0.f;
+        const float seed = td.mse_scale * r;  // dL/dd for L = mean (d - target)^2
+        sq = td.inv_b * (r * r);
+        *seedp = seed;
+        if (valid && td.seed_out) {  // for the reductions from the dumps (FP32)
+          td.seed_out[q] = seed;
+          td.sq_out[q] = sq;
+        }
+      }
+      if (td.bsum) {
+        // db_out = sum_i seed_i and the loss, over the tile (fixed butterfly), then
+        // over this workgroup's tiles in order
+        float sd = *seedp;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          sd += __shfl_xor(sd, off);
+          sq += __shfl_xor(sq, off);
+        }
+        if (n == 0) {
+          td.row(14)[0] += sd;
+          td.row(15)[0] += sq;
+        }
       }
     }
-    dump_tile<W, MODE>(td.act, td.h(3), td.ldb, td.q0, td.nvalid);
+    // h4 is needed only for dL/dw_out = sum_i seed_i h4_i: summed here when the
+    // tile engine keeps the bias sums, else written out
+    const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.xin};
+    dump_tile<W, MODE>(td.act, td.stage, td.h(3), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
     __syncthreads();  // h4 fully read before g4 overwrites the tile; seeds written
   }
   static_for<MT>([&](auto I) {
@@ -735,7 +828,11 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   __syncthreads();
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
   // overwritten only after the following K loop and its barrier
-  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid);
+  if constexpr (TRAIN) {  // h2, h3, or g4 (with db4 = sum_i g4_i)
+    const DumpSums sm{td.row(3), nullptr, nullptr, td.xin};
+    dump_tile<W, MODE>(td.act, td.stage, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid,
+                       (L == 2 && td.bsum) ? &sm : nullptr);
+  }
 }
 
 template <int W, int MODE, int L, bool TRAIN>
@@ -782,7 +879,10 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
     write_packed<W, MODE, RA>(ln, acc);
   }
   __syncthreads();
-  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.g(L), td.ldb, td.q0, td.nvalid);  // g3 or g2
+  if constexpr (TRAIN) {  // g3 or g2, with their bias sums
+    const DumpSums sm{td.row(L), nullptr, nullptr, td.xin};
+    dump_tile<W, MODE>(td.act, td.stage, td.g(L), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr);
+  }
 }
 
 // Last reverse layer: g1 = (W2^T g2) * SiLU'(z1) with z1 recomputed, then the
@@ -846,7 +946,10 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
       });
     });
     __syncthreads();
-    dump_tile<W, MODE>(td.act, td.g(0), td.ldb, td.q0, td.nvalid);
+    // g1 is needed only for db1 and dW1 = sum_i g1_i v_i^T: summed here when the
+    // tile engine keeps the sums, else written out
+    const DumpSums sm{td.row(0), nullptr, td.row(5), td.xin};
+    dump_tile<W, MODE>(td.act, td.stage, td.g(0), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
   }
 }
 
@@ -935,6 +1038,19 @@ struct TileCtx {
     }
   }
 };
+
+// LDS that training adds after the query's own: the fused loss's per-wave
+// partial sums ([waves][64]) and, for pure BF16, the per-workgroup sums of
+// TileDump::bsum ([kTrainSumRows][W]).
+template <int W, int MODE>
+constexpr int train_extra_lds() {
+  return Geo<W, MODE>::NW * kTileQ * 4 + (MODE == kBF16 ? kTrainSumRows * W * 4 : 0);
+}
+template <int W, int MODE>
+__device__ __forceinline__ float* train_bsum(char* lds) {
+  if constexpr (MODE == kBF16) return reinterpret_cast<float*>(lds + Geo<W, MODE>::LDS_BYTES + Geo<W, MODE>::NW * kTileQ * 4);
+  return nullptr;
+}
 
 // One tile: 64 points of knot kk starting at point q0 (dense), or pair-list
 // entries q0 .. q0+63 (pairs).  Every thread of the workgroup calls it; it ends
@@ -1031,10 +1147,12 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.nvalid = (int)(qlimit - q0 < kTileQ ? qlimit - q0 : kTileQ);
     td.layer_elems = (size_t)W * job.ldb;
     td.elem_bytes = MODE == kFP32 ? 4 : 2;
-    // the fused loss's partial sums: the idle half of a pure-BF16 tile, or the
-    // reduction buffer when it has its own space
-    static_assert(!G::RED_IN_ACT || MODE == kBF16, "training tile layout");
-    td.dred = G::RED_IN_ACT ? reinterpret_cast<float*>(tc.act + G::ACT_BYTES / 2) : red;
+    // LDS beyond the query's own: the fused loss's partial sums ([waves][64]); the
+    // idle half of a pure-BF16 tile stages the dumps
+    td.stage = tc.act + G::ACT_BYTES / 2;
+    td.dred = reinterpret_cast<float*>(tc.act + G::LDS_BYTES);
+    td.bsum = train_bsum<W, MODE>(tc.act);
+    td.width = W;
     td.xin = xin;
     td.target = job.seed ? nullptr : job.target;
     td.seed_out = job.seed_out;
@@ -1044,7 +1162,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   }
   fwd_input<W, MODE, PAIRS, SPH>(ln, b);
   __syncthreads();
-  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
+  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.stage, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
 
   // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
   float sp[2][MT][2][16];
@@ -1173,9 +1291,13 @@ __device__ __forceinline__ void report_overflow(const DevNet& net, const TileCtx
 template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false, bool GATHER = false, bool SPH = false>
 __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
-  __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES + (TRAIN ? train_extra_lds<W, MODE>() : 0)];
   __shared__ uint32_t ovf;
   TileCtx<W, MODE> tc(lds, &ovf, net, threadIdx.x);
+  float* bsum = TRAIN ? train_bsum<W, MODE>(lds) : nullptr;
+  if (bsum) {  // ordered before the first tile's sums by its barriers
+    for (int j = threadIdx.x; j < kTrainSumRows * W; j += Geo<W, MODE>::THREADS) bsum[j] = 0.f;
+  }
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (PAIRS) {
@@ -1194,6 +1316,11 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(cons
       process_tile<W, MODE, false, false, false, SPH>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
     }
   }
+  if (bsum) {  // this workgroup's sums; summed over workgroups in order afterwards
+    __syncthreads();
+    for (int j = threadIdx.x; j < kTrainSumRows * W; j += Geo<W, MODE>::THREADS)
+      job.bias_part[(int64_t)j * gridDim.x + blockIdx.x] = bsum[j];
+  }
   report_overflow<W, MODE>(net, tc);
 }
 
@@ -1207,10 +1334,10 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   const int64_t ntiles = PAIRS ? (job.npairs + kTileQ - 1) / kTileQ
                                : (job.tile_off ? job.ntiles_bound : job.K * ((job.Np + kTileQ - 1) / kTileQ));
   if (ntiles <= 0) return hipSuccess;
-  const int64_t slots = (int64_t)num_cu * OCC;
-  const int grid = (int)(ntiles < slots ? ntiles : slots);
+  const int grid = fused_grid(ntiles, num_cu);
   if constexpr (PAIRS && W == 256 && (MODE == kFP32 || MODE == kBF16) && !SPH) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
+      if (MODE == kBF16 && !job.bias_part) return hipErrorInvalidValue;  // the kernel writes its sums there
       hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job, 1,
                          ntiles);
       return hipGetLastError();

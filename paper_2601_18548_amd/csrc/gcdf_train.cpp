@@ -33,6 +33,7 @@ struct gcdf_trainer {
   void* dumpG = nullptr;
   float* dumpV = nullptr;
   float* mse = nullptr;  // fused MSE: per-sample seeds [ldb], then loss terms [ldb]
+  float* bias_part = nullptr;  // BF16: the training kernel's per-workgroup sums [kTrainSumRows][W][num_cu]
   float* partial = nullptr;
   const float* packed_from = nullptr;  // params pointer of the last packing
   // Table I loss workspace (allocated at its first use)
@@ -117,8 +118,12 @@ gcdf::Job training_job(const gcdf_trainer* tr, const float* knots, const float* 
   job.npairs = B;
   job.dumpH = tr->dumpH;
   job.dumpG = tr->dumpG;
-  job.dumpV = tr->dumpV;
   job.ldb = tr->ldb;
+  if (tr->mode == GCDF_FP32) {
+    job.dumpV = tr->dumpV;  // for dW1, reduced from the dumps
+  } else {
+    job.bias_part = tr->bias_part;  // the kernel sums what needs no GEMM
+  }
   return job;
 }
 
@@ -144,8 +149,21 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
     wj.out[l] = grad + o.Wl[l];
   }
   hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
-  // One pass over the batch for the rest (the partial buffer is free again: this
-  // follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
+  const int64_t ntiles = (B + gcdf::kTileQ - 1) / gcdf::kTileQ;
+  if (bf) {
+    // everything else was summed per workgroup by the training kernel: add the
+    // workgroups' sums (bias gradients, dw_out, dW1 column by column, db_out, loss)
+    gcdf::PartOut po{};
+    float* rows[5] = {grad + o.b1, grad + o.bl[0], grad + o.bl[1], grad + o.bl[2], grad + o.w5};
+    for (int r = 0; r < 5; ++r) po.base[r] = rows[r], po.stride[r] = 1, po.n[r] = W;
+    for (int c = 0; c < 9; ++c) po.base[5 + c] = grad + o.W1 + c, po.stride[5 + c] = 9, po.n[5 + c] = W;
+    po.base[14] = grad + o.b5, po.stride[14] = 1, po.n[14] = 1;
+    po.base[15] = loss, po.stride[15] = 1, po.n[15] = 1;
+    if (e == hipSuccess) e = gcdf::launch_part_sum(tr->bias_part, gcdf::fused_grid(ntiles, tr->num_cu), W, po, s);
+    return e;
+  }
+  // FP32: one pass over the batch for the rest (the partial buffer is free again:
+  // this follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
   // db1 = sum G_1; db_l = sum G_l; output layer dw_out = H_4 seed, db_out = sum seed;
   // the loss.  (Single-row V operands ignore the shared row stride ldb.)
   gcdf::RrJobs rj{};
@@ -155,7 +173,7 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
   rj.job[4] = {H(3), W, seed, 1, grad + o.w5, nullptr};
   rj.job[5] = {nullptr, 1, seed, 1, grad + o.b5, nullptr};
   if (sq) rj.job[6] = {nullptr, 1, sq, 1, loss, nullptr};
-  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, bf, B, tr->ldb, tr->partial, s);
+  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, false, B, tr->ldb, tr->partial, s);
   return e;
 }
 
@@ -195,6 +213,7 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(&tr->dumpG, dump);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->mse), (size_t)2 * tr->ldb * 4);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->bias_part), (size_t)std::max(tr->num_cu, 1) * gcdf::kTrainSumRows * W * 4);
   const size_t part = std::max({(size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
                                  (size_t)gcdf::rr_chunks(max_batch) * W * 10,
                                  (size_t)gcdf::kRrMaxJobs * gcdf::rr_multi_job_floats(W, max_batch)});
@@ -226,6 +245,7 @@ void gcdf_trainer_destroy(gcdf_trainer* tr) {
   (void)hipFree(tr->dumpG);
   (void)hipFree(tr->dumpV);
   (void)hipFree(tr->mse);
+  (void)hipFree(tr->bias_part);
   (void)hipFree(tr->partial);
   (void)hipFree(tr->t1);
   delete tr;
@@ -277,8 +297,10 @@ gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* k
   float* seed = tr->mse;
   float* sq = tr->mse + tr->ldb;
   job.target = target;
-  job.seed_out = seed;
-  job.sq_out = sq;
+  if (tr->mode == GCDF_FP32) {  // the seeds and loss terms for the reductions from the dumps
+    job.seed_out = seed;
+    job.sq_out = sq;
+  }
   job.mse_scale = (float)(2.0 / (double)B);
   job.inv_b = (float)(1.0 / (double)B);
   job.d = d;
