@@ -1,5 +1,7 @@
 // Query, training and packing kernels for gfx950 (MI355X) and their launchers;
 // the per-tile query body lives in gcdf_tile.h.
+#include <algorithm>
+
 #include "gcdf_tile.h"
 
 namespace gcdf {
@@ -602,9 +604,21 @@ hipError_t launch_fused(const DevNet& net, const Job& job, bool pairs, bool want
 // partial[chunk]; a second kernel adds the chunks in index order, so the result
 // does not depend on scheduling.
 // ----------------------------------------------------------------------------
-constexpr int kWgChunk = 2048;  // batch samples per chunk
+int64_t wgrad_chunk_len(int64_t B, int n, int width, int num_cu) {
+  const int ntile = (width / 128) * (width / 128);
+  const int64_t nch = std::max<int64_t>(1, num_cu / (ntile * std::max(n, 1)));
+  const int64_t per = (B + nch - 1) / nch;
+  return std::max<int64_t>(kTileQ, (per + kTileQ - 1) / kTileQ * kTileQ);
+}
 
-int wgrad_chunks(int64_t B) { return (int)((B + kWgChunk - 1) / kWgChunk); }
+int64_t wgrad_partial_floats(int64_t B, int width, int num_cu) {
+  int64_t most = 0;
+  for (int n = 1; n <= kWgMaxJobs; ++n) {
+    const int64_t L = wgrad_chunk_len(B, n, width, num_cu);
+    most = std::max(most, n * ((B + L - 1) / L));
+  }
+  return most * width * width;
+}
 
 template <int MODE>
 struct WgFrag;
@@ -622,7 +636,7 @@ struct WgFrag<kBF16> {
 // chunk's rows of G and H come from HBM once and are shared through that L2.
 template <int MODE>
 __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd, int64_t ldb, int64_t B, int nchunks,
-                                                         float* __restrict__ partial) {
+                                                         int64_t chunk_len, float* __restrict__ partial) {
   constexpr int kXcd = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tiles_n = Wd / 128, ntile = tiles_n * tiles_n;
@@ -636,8 +650,8 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
   const int job = (int)(grp / nchunks), chunk = (int)(grp % nchunks);
   const int f0 = (tile / tiles_n) * 128 + (wave >> 1) * 64;  // rows of out (G features)
   const int g0 = (tile % tiles_n) * 128 + (wave & 1) * 64;   // cols of out (H features)
-  const int64_t i0 = (int64_t)chunk * kWgChunk;
-  const int64_t i1 = i0 + kWgChunk < B ? i0 + kWgChunk : B;
+  const int64_t i0 = (int64_t)chunk * chunk_len;
+  const int64_t i1 = i0 + chunk_len < B ? i0 + chunk_len : B;
   f32x16 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -739,16 +753,20 @@ __global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks
 }
 
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int nchunks, hipStream_t s, bool accumulate) {
-  if (jobs.n < 1 || jobs.n > kWgMaxJobs || width % 128) return hipErrorInvalidValue;
+                             int num_cu, hipStream_t s, bool accumulate) {
+  if (jobs.n < 1 || jobs.n > kWgMaxJobs || width % 128 || B <= 0) return hipErrorInvalidValue;
+  const int64_t chunk_len = wgrad_chunk_len(B, jobs.n, width, num_cu);
+  const int nchunks = (int)((B + chunk_len - 1) / chunk_len);
   const int ntile = (width / 128) * (width / 128);
   const int64_t groups = (int64_t)jobs.n * nchunks;
   const int64_t per_xcd = (groups + 7) / 8;
   const unsigned grid = (unsigned)(8 * per_xcd * ntile);
   if (mode == kFP32)
-    hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, partial);
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, chunk_len,
+                       partial);
   else
-    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, partial);
+    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, chunk_len,
+                       partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)width * width;

@@ -221,8 +221,10 @@ hipError_t launch_fill_ones(unsigned long long* p, int64_t n, hipStream_t s);
 // ----------------------------------------------------------------------------
 // Up to kWgMaxJobs products in one launch: out_j[f][g] = sum_{i < B} G_j[f][i] H_j[g][i]
 // for f, g < width (a multiple of 128), via split-K partial sums in `partial`
-// (n * nchunks * width * width floats) reduced in a fixed order.  Rows of G and H
-// have stride ldb and hold zeros from B up to the next multiple of 64.
+// (wgrad_partial_floats(B, width, num_cu) floats) reduced in a fixed order.  Rows
+// of G and H have stride ldb and hold zeros from B up to the next multiple of 64.
+// The batch is cut into as few chunks as keep one workgroup per (product, chunk,
+// 128 x 128 output tile) within num_cu, so every workgroup runs in one round.
 constexpr int kWgMaxJobs = 3;
 struct WgradJobs {
   const void* G[kWgMaxJobs];
@@ -231,8 +233,11 @@ struct WgradJobs {
   int n;
 };
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int nchunks, hipStream_t s, bool accumulate = false);
-int wgrad_chunks(int64_t B);
+                             int num_cu, hipStream_t s, bool accumulate = false);
+// samples per chunk (a multiple of 64) for n products, and the floats of `partial`
+// any launch of up to kWgMaxJobs products over at most B samples needs
+int64_t wgrad_chunk_len(int64_t B, int n, int width, int num_cu);
+int64_t wgrad_partial_floats(int64_t B, int width, int num_cu);
 // For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
 // ldv, V[c] holding at least B entries) and bias[r] = sum_i A[r][i] (out / bias may be
 // NULL), i < B, with A (rows x batch) in the blocked feature-major layout of the

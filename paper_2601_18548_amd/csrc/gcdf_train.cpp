@@ -138,7 +138,6 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
   auto H = [&](int l) { return static_cast<const char*>(tr->dumpH) + l * layer; };
   auto G = [&](int l) { return static_cast<const char*>(tr->dumpG) + l * layer; };
   const bool bf = tr->mode != GCDF_FP32;
-  const int nch = gcdf::wgrad_chunks(B);
   const int gmode = bf ? gcdf::kBF16 : gcdf::kFP32;
   // dW_{l+1} = G_{l+1} H_l^T for the hidden layers 2..4, one launch
   gcdf::WgradJobs wj{};
@@ -148,7 +147,7 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
     wj.H[l] = H(l);
     wj.out[l] = grad + o.Wl[l];
   }
-  hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, nch, s);
+  hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, tr->num_cu, s);
   const int64_t ntiles = (B + gcdf::kTileQ - 1) / gcdf::kTileQ;
   if (bf) {
     // everything else was summed per workgroup by the training kernel: add the
@@ -214,7 +213,7 @@ gcdf_status gcdf_trainer_create(int32_t width, int32_t precision, int32_t device
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->dumpV), (size_t)9 * tr->ldb * 4);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->mse), (size_t)2 * tr->ldb * 4);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->bias_part), (size_t)std::max(tr->num_cu, 1) * gcdf::kTrainSumRows * W * 4);
-  const size_t part = std::max({(size_t)gcdf::kWgMaxJobs * gcdf::wgrad_chunks(max_batch) * W * W,
+  const size_t part = std::max({(size_t)gcdf::wgrad_partial_floats(max_batch, W, tr->num_cu),
                                  (size_t)gcdf::rr_chunks(max_batch) * W * 10,
                                  (size_t)gcdf::kRrMaxJobs * gcdf::rr_multi_job_floats(W, max_batch)});
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&tr->partial), part * 4);
@@ -382,7 +381,6 @@ gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float
   const int64_t ntiles = (B + gcdf::kTileQ - 1) / gcdf::kTileQ;
   if (e == hipSuccess) e = gcdf::launch_table1_tiles(tr->net, tj, (int)std::min<int64_t>(grid, ntiles), s);
   // 4. dW_l = sum zbar_l h_{l-1}^T + g_l hdot_{l-1}^T for the hidden layers
-  const int nch = gcdf::wgrad_chunks(B);
   gcdf::WgradJobs a{}, b{};
   a.n = b.n = 3;
   for (int l = 0; l < 3; ++l) {
@@ -392,8 +390,8 @@ gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float
     b.H[l] = Hd + l * layer;
     a.out[l] = b.out[l] = grad + o.Wl[l];
   }
-  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(a, W, gcdf::kFP32, ldb, B, tr->partial, nch, s, false);
-  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(b, W, gcdf::kFP32, ldb, B, tr->partial, nch, s, true);
+  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(a, W, gcdf::kFP32, ldb, B, tr->partial, tr->num_cu, s, false);
+  if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(b, W, gcdf::kFP32, ldb, B, tr->partial, tr->num_cu, s, true);
   // 5. input layer: dW_1 = sum zbar_1 v^T + g_1 u^T, db_1 = sum zbar_1; db_l = sum zbar_l
   float* rp = tr->partial;
   if (e == hipSuccess)

@@ -65,9 +65,10 @@ def test_weight_gradients_match_oracle(tr_mod, oracle_mod, precision, tol):
         assert err <= tol, name
 
 
-# A batch past the chunk sizes of the reductions: 4 weight-gradient GEMM chunks of
-# 2,048 samples (the last one 37), 13 row-reduction chunks of 512 (the last 37),
-# and a ragged last tile of 37 samples.
+# A batch past the chunk sizes of the reductions: on 256 compute units, 20
+# weight-gradient GEMM chunks of 320 samples (the last one 101), 13 row-reduction
+# chunks of 512 (FP32; the last 37), 97 tiles whose per-workgroup sums (BF16) are
+# added over 97 workgroups, and a ragged last tile of 37 samples.
 MULTI_B = 6181
 
 
