@@ -499,16 +499,20 @@ __device__ __forceinline__ uint32_t ordered_bits(float f) {
 // which spreads the 16 pieces written by 16 consecutive lanes over 16 different
 // bank groups, and those read by 16 consecutive lanes too.
 // BF16, with sums: the copy also adds, over the tile's samples i, to LDS rows
-// (per feature f) sum_i x[f][i] w_i (w_i = seed_i, or 1) and optionally
-// sum_i x[f][i] v_c(i) for the nine network inputs v_c, in a fixed order:
-// samples within a piece, pieces in order, then the threads sharing a feature in
-// order.  store false: the sums only, nothing written to HBM.
+// (per feature f) sum_i x[f][i] w_i (w_i = seed_i, or 1) in a fixed order
+// (samples within a piece, pieces in order, then the two lanes sharing a
+// feature), and optionally sum_i x[f][i] v_c(i) for the nine network inputs v_c
+// on the matrix cores (the pieces are the A fragments of a 32 x 32 x 16 product
+// over samples; v is split into BF16 hi + lo).  In the copy, wave w owns features
+// 32w .. 32w + 31, its lane halves taking alternate 8-sample blocks.  store
+// false: the sums only, nothing written to HBM.
 // ----------------------------------------------------------------------------
 struct DumpSums {
   float* row;          // [W]: sum_i x[f][i] w_i
   const float* seed;   // w_i = seed[i * XIN_FLOATS] (the records' seed slot), or NULL: w_i = 1
   float* in_rows;      // [9][W]: sum_i x[f][i] v_c(i), or NULL
-  const float* xin;    // per-query records: v = p' (slots 0..2), arm (slots 5..10)
+  const float* xin;    // per-query records
+  const __bf16* vt;    // the tile's inputs v_c(i) as BF16 hi [9][64], then lo [9][64]
 };
 
 template <int W, int MODE>
@@ -535,7 +539,6 @@ __device__ __forceinline__ void dump_tile(const char* act, char* stage, void* ds
     // consecutive queries, transposes it in registers and stages the 8 features'
     // 16-byte pieces of that query block; then every thread copies pieces out.
     static_assert(MODE == kBF16 && W * kTileQ * 2 <= Geo<W, MODE>::ACT_BYTES / 2, "staging needs a pure-BF16 tile");
-    static_assert(10 * Geo<W, MODE>::THREADS * 4 <= W * kTileQ * 2, "the sums' combine buffer shares the staging area");
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const char* a = act;
     constexpr int NG = W / 8;  // feature groups
@@ -566,39 +569,54 @@ __device__ __forceinline__ void dump_tile(const char* act, char* stage, void* ds
     constexpr int T = Geo<W, MODE>::THREADS;
     static_assert(T % W == 0, "a thread's pieces share one feature");
     constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
+    static_assert(T / 64 == W / 32 && NP == T * 4, "the copy: one 32-feature block per wave, 4 rounds");
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const int f = 32 * (threadIdx.x >> 6) + (lane & 31);
     __bf16* o = static_cast<__bf16*>(dst) + (q0 >> 3) * W * 8;
-    float part[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // row, then the 9 inputs
-    for (int P = threadIdx.x; P < NP; P += T) {
+    float part = 0.f;
+    f32x16 dacc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dacc[j] = 0.f;
+    const int c = lane & 31;  // input column of the v fragments
+#pragma unroll
+    for (int st = 0; st < kTileQ / 16; ++st) {  // 16 samples per round: blocks 2 st (lanes < 32), 2 st + 1
+      const int nb = 2 * st + half;
+      const int P = nb * W + f;
       const u32x4 v = *reinterpret_cast<const u32x4*>(stage + (P ^ ((P >> 4) & 7)) * 16);
       if (store) *reinterpret_cast<u32x4*>(o + P * 8) = v;
       if (sums) {
-        const int n0 = (P / W) * 8;  // word w: samples n0 + 2w (low half), n0 + 2w + 1
+        const int n0 = nb * 8;  // word w: samples n0 + 2w (low half), n0 + 2w + 1
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const uint32_t word = v[e >> 1];
           const float x = __uint_as_float((e & 1) ? (word & 0xffff0000u) : (word << 16));
-          const float* rec = sums->xin + (n0 + e) * XF;
-          part[0] += sums->seed ? x * sums->seed[(n0 + e) * XF] : x;
-          if (sums->in_rows) {
+          part += sums->seed ? x * sums->seed[(n0 + e) * XF] : x;
+        }
+        if (sums->in_rows) {
+          // A: 8 samples of feature f (lane = (f % 32, half)); B: v_c of the same 8
+          // samples (lane = (c, half)), hi then lo
+          const bf16x8 a = __builtin_bit_cast(bf16x8, v);
+          bf16x8 bh, bl;
+          if (c < 9) {
+            bh = *reinterpret_cast<const bf16x8*>(sums->vt + c * kTileQ + n0);
+            bl = *reinterpret_cast<const bf16x8*>(sums->vt + (9 + c) * kTileQ + n0);
+          } else {
 #pragma unroll
-            for (int c = 0; c < 9; ++c) part[1 + c] += x * rec[c < 3 ? c : c + 2];
+            for (int e = 0; e < 8; ++e) bh[e] = bl[e] = (__bf16)0.f;
           }
+          dacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bh, dacc, 0, 0, 0);
+          dacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, dacc, 0, 0, 0);
         }
       }
     }
     if (sums) {
-      const int nv = sums->in_rows ? 10 : 1;
-      float* cb = reinterpret_cast<float*>(stage);
-      __syncthreads();  // every thread has copied its pieces out of the staging area
-      for (int k = 0; k < nv; ++k) cb[k * T + threadIdx.x] = part[k];
-      __syncthreads();
-      if (threadIdx.x < W) {
-        for (int k = 0; k < nv; ++k) {
-          float t = cb[k * T + threadIdx.x];
+      part += __shfl_xor(part, 32);
+      if (half == 0) sums->row[f] += part;
+      if (sums->in_rows && c < 9) {
+        // C layout: lane (c, half) holds rows 8 (j/4) + 4 half + j%4 of the wave's 32 features
+        float* r = sums->in_rows + c * W + 32 * (threadIdx.x >> 6);
 #pragma unroll
-          for (int u = 1; u < T / W; ++u) t += cb[k * T + threadIdx.x + u * W];
-          (k == 0 ? sums->row : sums->in_rows + (k - 1) * W)[threadIdx.x] += t;
-        }
+        for (int j = 0; j < 16; ++j) r[8 * (j >> 2) + 4 * half + (j & 3)] += dacc[j];
       }
     }
   }
@@ -649,6 +667,7 @@ struct TileDump {
   // 5..13 dW1[:, c] = sum_i g1_i v_c(i), row 14 (first entry) db_out = sum_i seed_i,
   // row 15 (first entry) the fused loss sum_i (d_i - target_i)^2 / B
   float* bsum;
+  __bf16* vt;  // with bsum: the tile's network inputs, transposed, BF16 hi [9][64] then lo
   int width;
   __device__ __forceinline__ float* row(int r) const { return bsum ? bsum + r * width : nullptr; }
   __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
@@ -780,7 +799,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
     }
     // h4 is needed only for dL/dw_out = sum_i seed_i h4_i: summed here when the
     // tile engine keeps the bias sums, else written out
-    const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.xin};
+    const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.xin, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.h(3), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
     __syncthreads();  // h4 fully read before g4 overwrites the tile; seeds written
   }
@@ -829,7 +848,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
   // overwritten only after the following K loop and its barrier
   if constexpr (TRAIN) {  // h2, h3, or g4 (with db4 = sum_i g4_i)
-    const DumpSums sm{td.row(3), nullptr, nullptr, td.xin};
+    const DumpSums sm{td.row(3), nullptr, nullptr, td.xin, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid,
                        (L == 2 && td.bsum) ? &sm : nullptr);
   }
@@ -880,7 +899,7 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   }
   __syncthreads();
   if constexpr (TRAIN) {  // g3 or g2, with their bias sums
-    const DumpSums sm{td.row(L), nullptr, nullptr, td.xin};
+    const DumpSums sm{td.row(L), nullptr, nullptr, td.xin, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.g(L), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr);
   }
 }
@@ -919,16 +938,19 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
           const float c = PAIRS ? arm_term(wa[3], wb[0], wb[1], wb[2], wb[3], wc[0], wc[1], x + 5) : cr;
           const float z = input_preact_t<SPH>(c, wa[0], wa[1], wa[2], wc[2], x);
           const float g1 = acc[i][nt][4 * g + r] * silu_prime_only(z);
-          epart[nt][0] += wa[0] * g1;
-          epart[nt][1] += wa[1] * g1;
-          epart[nt][2] += wa[2] * g1;
-          epart[nt][3] += wb[0] * g1;
-          epart[nt][4] += wb[1] * g1;
-          epart[nt][5] += wb[2] * g1;
-          epart[nt][6] += wb[3] * g1;
-          epart[nt][7] += wc[0] * g1;
-          epart[nt][8] += wc[1] * g1;
-          if constexpr (TRAIN) g1keep[i][nt][4 * g + r] = g1;
+          if constexpr (TRAIN) {
+            g1keep[i][nt][4 * g + r] = g1;  // training needs g1, not J
+          } else {
+            epart[nt][0] += wa[0] * g1;
+            epart[nt][1] += wa[1] * g1;
+            epart[nt][2] += wa[2] * g1;
+            epart[nt][3] += wb[0] * g1;
+            epart[nt][4] += wb[1] * g1;
+            epart[nt][5] += wb[2] * g1;
+            epart[nt][6] += wb[3] * g1;
+            epart[nt][7] += wc[0] * g1;
+            epart[nt][8] += wc[1] * g1;
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -948,7 +970,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
     __syncthreads();
     // g1 is needed only for db1 and dW1 = sum_i g1_i v_i^T: summed here when the
     // tile engine keeps the sums, else written out
-    const DumpSums sm{td.row(0), nullptr, td.row(5), td.xin};
+    const DumpSums sm{td.row(0), nullptr, td.row(5), td.xin, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.g(0), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
   }
 }
@@ -1041,14 +1063,20 @@ struct TileCtx {
 
 // LDS that training adds after the query's own: the fused loss's per-wave
 // partial sums ([waves][64]) and, for pure BF16, the per-workgroup sums of
-// TileDump::bsum ([kTrainSumRows][W]).
+// TileDump::bsum ([kTrainSumRows][W]) and the tile's transposed inputs
+// (TileDump::vt).
 template <int W, int MODE>
 constexpr int train_extra_lds() {
-  return Geo<W, MODE>::NW * kTileQ * 4 + (MODE == kBF16 ? kTrainSumRows * W * 4 : 0);
+  return Geo<W, MODE>::NW * kTileQ * 4 + (MODE == kBF16 ? kTrainSumRows * W * 4 + 2 * 9 * kTileQ * 2 : 0);
 }
 template <int W, int MODE>
 __device__ __forceinline__ float* train_bsum(char* lds) {
   if constexpr (MODE == kBF16) return reinterpret_cast<float*>(lds + Geo<W, MODE>::LDS_BYTES + Geo<W, MODE>::NW * kTileQ * 4);
+  return nullptr;
+}
+template <int W, int MODE>
+__device__ __forceinline__ __bf16* train_vt(char* lds) {
+  if constexpr (MODE == kBF16) return reinterpret_cast<__bf16*>(train_bsum<W, MODE>(lds) + kTrainSumRows * W);
   return nullptr;
 }
 
@@ -1117,6 +1145,18 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
     // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact)
     x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : 1.f;
+    if constexpr (TRAIN && MODE == kBF16) {
+      // the network inputs transposed and split into BF16 hi + lo, for dW1 on the
+      // matrix cores (the ragged tail's inputs meet zero gradients)
+      __bf16* vt = train_vt<W, MODE>(tc.act);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const float v = x[c < 3 ? c : c + 2];
+        const __bf16 hi = (__bf16)v;
+        vt[c * kTileQ + tid] = hi;
+        vt[(9 + c) * kTileQ + tid] = (__bf16)(v - (float)hi);
+      }
+    }
     if constexpr (SPH) x[kXinRadius] = pxyz[3];  // the radius passes through the rigid transform
     if constexpr (PAIRS) {
       if (job.dumpV) {
@@ -1152,6 +1192,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.stage = tc.act + G::ACT_BYTES / 2;
     td.dred = reinterpret_cast<float*>(tc.act + G::LDS_BYTES);
     td.bsum = train_bsum<W, MODE>(tc.act);
+    td.vt = train_vt<W, MODE>(tc.act);
     td.width = W;
     td.xin = xin;
     td.target = job.seed ? nullptr : job.target;
@@ -1245,7 +1286,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     // outputs are streamed with non-temporal stores: written once and never read
     // here, they would otherwise evict the packed weights from L2
     if (valid && job.d) __builtin_nontemporal_store(dv, job.d + out);
-    if (valid && job.J && want_grad) {
+    if (!TRAIN && valid && job.J && want_grad) {  // (training computes g1, not J)
       const float* x = xin + n * XF;
       const float cs = x[3], sn = x[4];
       const float* e = vals + 1;
@@ -1337,7 +1378,8 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   const int grid = fused_grid(ntiles, num_cu);
   if constexpr (PAIRS && W == 256 && (MODE == kFP32 || MODE == kBF16) && !SPH) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
-      if (MODE == kBF16 && !job.bias_part) return hipErrorInvalidValue;  // the kernel writes its sums there
+      // the kernel writes its sums to bias_part, and no J
+      if ((MODE == kBF16 && !job.bias_part) || job.J) return hipErrorInvalidValue;
       hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job, 1,
                          ntiles);
       return hipGetLastError();
