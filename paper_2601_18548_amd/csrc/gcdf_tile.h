@@ -660,6 +660,7 @@ struct TileDump {
   const float* target;
   float* seed_out;
   float* sq_out;
+  float* d_out;  // the distances, when asked for
   float mse_scale, inv_b;
   // per-workgroup sums over its samples (LDS, [kTrainSumRows][width]; NULL when
   // these gradients are reduced from the dumps instead): rows 0..3 the bias
@@ -777,6 +778,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         const float seed = td.mse_scale * r;  // dL/dd for L = mean (d - target)^2
         sq = td.inv_b * (r * r);
         *seedp = seed;
+        if (valid && td.d_out) td.d_out[q] = dv;
         if (valid && td.seed_out) {  // for the reductions from the dumps (FP32)
           td.seed_out[q] = seed;
           td.sq_out[q] = sq;
@@ -1198,6 +1200,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.target = job.seed ? nullptr : job.target;
     td.seed_out = job.seed_out;
     td.sq_out = job.sq_out;
+    td.d_out = job.seed ? nullptr : job.d;
     td.mse_scale = job.mse_scale;
     td.inv_b = job.inv_b;
   }
@@ -1241,74 +1244,77 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   }
 
   // ---- reduce d and e over the rows: lane halves, then waves (fixed order) ----
-#pragma unroll
-  for (int nt = 0; nt < 2; ++nt) {
-    dpart[nt] += __shfl_xor(dpart[nt], 32);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
-  }
-  // the reduction buffer may share the activation tile: every wave must have
-  // finished reading it
-  if constexpr (G::RED_IN_ACT) __syncthreads();
-  if (ln.h == 0) {
+  // (training needs neither: the fused loss finished d inside the tile)
+  if constexpr (!TRAIN) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-      const int n = 32 * nt + ln.n0;
-      red[(ln.wave * G::RED_VALS + 0) * kTileQ + n] = dpart[nt];
+      dpart[nt] += __shfl_xor(dpart[nt], 32);
 #pragma unroll
-      for (int c = 0; c < 9; ++c) red[(ln.wave * G::RED_VALS + 1 + c) * kTileQ + n] = epart[nt][c];
+      for (int c = 0; c < 9; ++c) epart[nt][c] += __shfl_xor(epart[nt][c], 32);
     }
-  }
-  __syncthreads();
-
-  // ---- per query: final sums, chain rule, stores, per-knot minimum ----
-  if (tid < kTileQ) {
-    // recomputed here rather than kept from the prologue (the compiler would
-    // otherwise hold q0 + tid through the whole tile, in a spill slot)
-    int n = tid;
-    asm volatile("" : "+v"(n));
-    float vals[G::RED_VALS];
+    // the reduction buffer may share the activation tile: every wave must have
+    // finished reading it
+    if constexpr (G::RED_IN_ACT) __syncthreads();
+    if (ln.h == 0) {
 #pragma unroll
-    for (int c = 0; c < G::RED_VALS; ++c) {
-      float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
+      for (int nt = 0; nt < 2; ++nt) {
+        const int n = 32 * nt + ln.n0;
+        red[(ln.wave * G::RED_VALS + 0) * kTileQ + n] = dpart[nt];
 #pragma unroll
-      for (int w = 1; w < G::NW; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
-      vals[c] = sum;
-    }
-    if constexpr (rev_scale<MODE>() != 1.0f) {
-#pragma unroll
-      for (int c = 1; c < G::RED_VALS; ++c) vals[c] *= 1.0f / rev_scale<MODE>();
-    }
-    const float dv = vals[0] + *net.b5p;
-    const int64_t q = q0 + n;
-    const bool valid = q < qlimit;
-    const int64_t out = (PAIRS || GATHER) ? q : kk * job.Np + q;
-    // outputs are streamed with non-temporal stores: written once and never read
-    // here, they would otherwise evict the packed weights from L2
-    if (valid && job.d) __builtin_nontemporal_store(dv, job.d + out);
-    if (!TRAIN && valid && job.J && want_grad) {  // (training computes g1, not J)
-      const float* x = xin + n * XF;
-      const float cs = x[3], sn = x[4];
-      const float* e = vals + 1;
-      float* Jo = job.J + out * kInDim;
-      __builtin_nontemporal_store(-(cs * e[0] - sn * e[1]), Jo + 0);
-      __builtin_nontemporal_store(-(sn * e[0] + cs * e[1]), Jo + 1);
-      __builtin_nontemporal_store(e[0] * x[1] - e[1] * x[0], Jo + 2);
-#pragma unroll
-      for (int c = 3; c < 9; ++c) __builtin_nontemporal_store(e[c], Jo + c);
-    }
-    if constexpr (!PAIRS) {
-      if (job.minkey) {
-        unsigned long long key = valid ? (((unsigned long long)ordered_bits(dv) << 32) | (uint32_t)q) : ~0ull;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          unsigned long long o = __shfl_xor(key, off);
-          key = o < key ? o : key;
-        }
-        if (n == 0 && key != ~0ull) atomicMin(job.minkey + kk, key);
+        for (int c = 0; c < 9; ++c) red[(ln.wave * G::RED_VALS + 1 + c) * kTileQ + n] = epart[nt][c];
       }
     }
-  }
+    __syncthreads();
+
+    // ---- per query: final sums, chain rule, stores, per-knot minimum ----
+    if (tid < kTileQ) {
+      // recomputed here rather than kept from the prologue (the compiler would
+      // otherwise hold q0 + tid through the whole tile, in a spill slot)
+      int n = tid;
+      asm volatile("" : "+v"(n));
+      float vals[G::RED_VALS];
+#pragma unroll
+      for (int c = 0; c < G::RED_VALS; ++c) {
+        float sum = red[(0 * G::RED_VALS + c) * kTileQ + n];
+#pragma unroll
+        for (int w = 1; w < G::NW; ++w) sum += red[(w * G::RED_VALS + c) * kTileQ + n];
+        vals[c] = sum;
+      }
+      if constexpr (rev_scale<MODE>() != 1.0f) {
+#pragma unroll
+        for (int c = 1; c < G::RED_VALS; ++c) vals[c] *= 1.0f / rev_scale<MODE>();
+      }
+      const float dv = vals[0] + *net.b5p;
+      const int64_t q = q0 + n;
+      const bool valid = q < qlimit;
+      const int64_t out = (PAIRS || GATHER) ? q : kk * job.Np + q;
+      // outputs are streamed with non-temporal stores: written once and never read
+      // here, they would otherwise evict the packed weights from L2
+      if (valid && job.d) __builtin_nontemporal_store(dv, job.d + out);
+      if (!TRAIN && valid && job.J && want_grad) {  // (training computes g1, not J)
+        const float* x = xin + n * XF;
+        const float cs = x[3], sn = x[4];
+        const float* e = vals + 1;
+        float* Jo = job.J + out * kInDim;
+        __builtin_nontemporal_store(-(cs * e[0] - sn * e[1]), Jo + 0);
+        __builtin_nontemporal_store(-(sn * e[0] + cs * e[1]), Jo + 1);
+        __builtin_nontemporal_store(e[0] * x[1] - e[1] * x[0], Jo + 2);
+#pragma unroll
+        for (int c = 3; c < 9; ++c) __builtin_nontemporal_store(e[c], Jo + c);
+      }
+      if constexpr (!PAIRS) {
+        if (job.minkey) {
+          unsigned long long key = valid ? (((unsigned long long)ordered_bits(dv) << 32) | (uint32_t)q) : ~0ull;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            unsigned long long o = __shfl_xor(key, off);
+            key = o < key ? o : key;
+          }
+          if (n == 0 && key != ~0ull) atomicMin(job.minkey + kk, key);
+        }
+      }
+    }
+  }  // !TRAIN
   // The next tile's prologue rewrites xin and crow: every wave has passed the
   // barrier above (crow's last reader), and xin's readers here are wave 0,
   // which also writes it, in program order.
@@ -1378,8 +1384,8 @@ static hipError_t launch_t(const DevNet& net, const Job& job, bool want_grad, in
   const int grid = fused_grid(ntiles, num_cu);
   if constexpr (PAIRS && W == 256 && (MODE == kFP32 || MODE == kBF16) && !SPH) {  // training: width 256, FP32 or BF16
     if (job.dumpH) {
-      // the kernel writes its sums to bias_part, and no J
-      if ((MODE == kBF16 && !job.bias_part) || job.J) return hipErrorInvalidValue;
+      // the kernel writes its sums to bias_part, no J, and d only with the fused loss
+      if ((MODE == kBF16 && !job.bias_part) || job.J || (job.d && !job.target)) return hipErrorInvalidValue;
       hipLaunchKernelGGL((fused_query<W, MODE, true, OCC, true>), dim3(grid), dim3((Geo<W, MODE>::THREADS)), 0, s, net, job, 1,
                          ntiles);
       return hipGetLastError();
