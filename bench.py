@@ -17,7 +17,9 @@ Prints one JSON line: pairs (queries) per second, plus
   serving      : p50 / p99 latency of a Poisson request trace through gcdf_submit;
   constraints  : partitions around a 128-knot trajectory, the CSR query, the
                  Jacobian pattern and the single-step projection (HBM roofline);
-  training     : steps/s of the width-256 training step (batch 65,536, Adam);
+  training     : steps/s of the width-256 training step (batch 65,536, Adam), with
+                 the FP64 oracle's gradient timed on a 1,024-sample sub-batch and
+                 the step's gradient on those samples against it;
   training_table1: the same with the paper's four-term Table I loss (FP32).
 The serving and training legs carry their own roofline objects (algorithmic
 TFLOP/s over wall time against the BF16, resp. FP32, dense peak); the FP32
@@ -325,7 +327,7 @@ def sphere_bench(g, torch, point_kernel_ms: float, reps: int = 10):
             "vs_point_kernel": point_kernel_ms / ms}
 
 
-def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
+def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int = 256, cpu: bool = True):
     """Training step of the width-256 network: MSE against a seeded teacher's
     distances plus N(0, 1e-3) noise, hand-written forward/backward behind
     torch.autograd, Adam (lr 0.005) on FP32 master weights, BF16 matrix cores."""
@@ -350,16 +352,41 @@ def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int =
         loss = train.mse_step(params, opt, tr, kt, pt, y)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    tr.close()
     # algorithmic work per sample: forward 6 W^2, reverse 6 W^2, weight gradients 6 W^2
     fl = 18 * width * width * batch
     tf = fl * steps / el / 1e12
-    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "samples_per_s": batch * steps / el,
-            "batch": batch, "width": width, "precision": "bf16 (FP32 master weights, FP32 accumulate)",
-            "tflops_algorithmic": tf,
-            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
-                         "frac": tf / PEAK_TFLOPS["bf16"], "work": "18 W^2 FLOP per sample, whole step"},
-            "loss_first": float(loss0.item()) if loss0 is not None else None, "loss_last": float(loss.item())}
+    out = {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3, "samples_per_s": batch * steps / el,
+           "batch": batch, "width": width, "precision": "bf16 (FP32 master weights, FP32 accumulate)",
+           "tflops_algorithmic": tf,
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                        "frac": tf / PEAK_TFLOPS["bf16"], "work": "18 W^2 FLOP per sample, whole step"},
+           "loss_first": float(loss0.item()) if loss0 is not None else None, "loss_last": float(loss.item())}
+    if cpu:
+        # the FP64 oracle's loss gradient on a 1,024-sample sub-batch at the trained
+        # parameters, timed, and the library's gradient on the same samples against it
+        import numpy as np
+
+        import oracle
+
+        n = 1024
+        blob = student.to_blob()[:wl.BLOB_HEADER_BYTES] + params.detach().cpu().numpy().astype("<f4").tobytes()
+        ys = y[:n].contiguous()
+        _, g_gpu = tr.mse(params.detach(), kt[:n].contiguous(), pt[:n].contiguous(), ys)
+        g_gpu = g_gpu.cpu().numpy().astype(np.float64)
+        t1 = time.perf_counter()
+        _, gref = oracle.mse_grad(blob, k[:n], p[:n], ys.cpu().numpy())
+        cpu_s = time.perf_counter() - t1
+        errs, off = [], 0
+        for a in gref:
+            seg = g_gpu[off:off + a.size]
+            off += a.size
+            errs.append(float(np.linalg.norm(seg - a.ravel()) / max(np.linalg.norm(a), 1e-30)))
+        out["cpu_baseline"] = {"value": n / cpu_s, "unit": "samples/s (loss + weight gradient)", "cores": 1,
+                               "kind": "oracle", "sample": "the first %d samples of the batch, FP64, %.2f s" % (n, cpu_s)}
+        out["gradient_vs_oracle"] = {"samples": n, "max_rel_err_per_array": max(errs),
+                                     "arrays": "W1 b1 W2 b2 W3 b3 W4 b4 w_out b_out, norm-wise"}
+    tr.close()
+    return out
 
 
 def table1_bench(g, torch, steps: int, warmup: int, batch: int = 65536, width: int = 256):
@@ -599,7 +626,7 @@ def main():
         out["sphere"] = sphere_bench(g, torch, kernel_ms)
         print("bench: sphere %s" % json.dumps(out["sphere"]), file=sys.stderr, flush=True)
     if args.train_steps > 0:
-        out["training"] = train_bench(torch, args.train_steps, 3)
+        out["training"] = train_bench(torch, args.train_steps, 3, cpu=not args.no_cpu_baseline)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
     if args.train_steps > 0:
         out["training_table1"] = table1_bench(g, torch, max(5, args.train_steps // 4), 2)
