@@ -777,128 +777,18 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
 
 // Row reductions over the batch in two fixed-order passes, A in the blocked
 // feature-major layout of dump_tile.  Pass 1: grid (256-row group, chunk of
-// kRrChunk samples); a thread owns one row and walks the chunk's 16-byte blocks
-// in order (a workgroup reads 4 KB contiguous per block), V is read uniformly.
-// Pass 2 adds the chunks in index order.  The result does not depend on scheduling.
+// kRrChunk samples, job); a thread owns one row and walks the chunk's 16-byte
+// blocks in order (a workgroup reads 4 KB contiguous per block), V is read
+// uniformly.  Pass 2 adds the chunks in index order.  The result does not depend
+// on scheduling.
 constexpr int kRrChunk = 512;
 constexpr int kRrMaxC = 9;
 
 int rr_chunks(int64_t B) { return (int)((B + kRrChunk - 1) / kRrChunk); }
 
-template <bool BF>
-__global__ __launch_bounds__(256) void rr_partial_kernel(const void* __restrict__ Av, int rows, int64_t B,
-                                                          const float* __restrict__ V, int64_t ldv, int C,
-                                                          float* __restrict__ partial) {
-  constexpr int S = BF ? 8 : 4;  // samples per 16-byte block
-  __shared__ float sv[kRrMaxC][kRrChunk];  // this chunk of V (zero past B)
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.y * kRrChunk;
-  const int64_t i1 = i0 + kRrChunk < B ? i0 + kRrChunk : B;
-  for (int c = 0; c < C; ++c)
-    for (int k = threadIdx.x; k < kRrChunk; k += 256) sv[c][k] = i0 + k < i1 ? V[(int64_t)c * ldv + i0 + k] : 0.f;
-  __syncthreads();
-  if (r >= rows) return;
-  float acc[kRrMaxC + 1];
-#pragma unroll
-  for (int c = 0; c <= kRrMaxC; ++c) acc[c] = 0.f;
-  // NB blocks per round: their loads are issued together, then consumed in order
-  constexpr int NB = 8;
-  static_assert(NB * S <= kTileQ && kRrChunk % (NB * S) == 0, "rounds must stay in the zero-padded tail");
-  typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
-  for (int64_t i = i0; i < i1; i += NB * S) {
-    float a[NB][S];
-    // A round covers NB * S (64 or 32) samples from a multiple of that size below B,
-    // so it stays inside the zero-padded tail (rows are zero from B to the next
-    // multiple of 64): the loads need no condition and are issued together.
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int64_t blk = (((i + k * S) / S) * rows + r) * S;
-      if constexpr (BF) {
-        const v8 x = *reinterpret_cast<const v8*>(static_cast<const __bf16*>(Av) + blk);
-#pragma unroll
-        for (int u = 0; u < S; ++u) a[k][u] = (float)x[u];
-      } else {
-        const f32x4 x = *reinterpret_cast<const f32x4*>(static_cast<const float*>(Av) + blk);
-#pragma unroll
-        for (int u = 0; u < S; ++u) a[k][u] = x[u];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-#pragma unroll
-      for (int u = 0; u < S; ++u) acc[kRrMaxC] += a[k][u];
-    // V from LDS: every lane reads the same word (a broadcast)
-    const int j0 = (int)(i - i0);
-    for (int c = 0; c < C; ++c) {
-      float t = acc[c];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const f32x4* vp = reinterpret_cast<const f32x4*>(&sv[c][j0 + k * S]);
-#pragma unroll
-        for (int h = 0; h < S / 4; ++h) {
-          const f32x4 vv = vp[h];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) t += a[k][4 * h + u] * vv[u];
-        }
-      }
-      acc[c] = t;
-    }
-  }
-  float* out = partial + ((int64_t)blockIdx.y * rows + r) * (kRrMaxC + 1);
-#pragma unroll
-  for (int c = 0; c <= kRrMaxC; ++c) out[c] = acc[c];
-}
-
-__global__ void rr_sum_kernel(const float* __restrict__ partial, int nchunks, int rows, int C, float* __restrict__ out,
-                              float* __restrict__ bias, int accum) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = (int)(t / (kRrMaxC + 1)), c = (int)(t % (kRrMaxC + 1));
-  if (r >= rows || (c >= C && c != kRrMaxC)) return;
-  float s = 0.f;
-#pragma unroll 8
-  for (int k = 0; k < nchunks; ++k) s += partial[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
-  if (c == kRrMaxC) {
-    if (bias) bias[r] = accum ? bias[r] + s : s;
-  } else if (out) {
-    out[(int64_t)r * C + c] = accum ? out[(int64_t)r * C + c] + s : s;
-  }
-}
-
-// One workgroup: out = sum_{i < n} x[i], strided per thread then a fixed tree.
-__global__ __launch_bounds__(256) void vec_sum_kernel(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
-  __shared__ float red[256];
-  float s = 0.f;
-#pragma unroll 8
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
-}
-
-hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
-                             float* out, float* bias, float* partial, hipStream_t s, bool accumulate) {
-  if (C > kRrMaxC || rows <= 0 || B <= 0) return hipErrorInvalidValue;
-  const int nch = rr_chunks(B);
-  const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nch);
-  if (a_is_bf16)
-    hipLaunchKernelGGL(rr_partial_kernel<true>, grid, dim3(256), 0, s, A, rows, B, V, ldv, C, partial);
-  else
-    hipLaunchKernelGGL(rr_partial_kernel<false>, grid, dim3(256), 0, s, A, rows, B, V, ldv, C, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t n = (int64_t)rows * (kRrMaxC + 1);
-  hipLaunchKernelGGL(rr_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nch, rows, C, out,
-                     bias, accumulate ? 1 : 0);
-  return hipGetLastError();
-}
-
-// Several row reductions in one pass each (see RrJobs): grid (row group, chunk,
-// job); job j's partial sums at partial + j * job_stride in the layout of
-// rr_partial_kernel.  A job without A reduces a single row of ones (out = sum V).
+// Several row reductions in one pass each (see RrJobs): job j's partial sums at
+// partial + j * job_stride, [chunk][row][kRrMaxC + 1] (the last slot the row sum).
+// A job without A reduces a single row of ones (out = sum V).
 template <bool BF>
 __global__ __launch_bounds__(256) void rr_multi_partial_kernel(RrJobs jobs, int64_t B, int64_t ldv,
                                                                float* __restrict__ partial, int64_t job_stride) {
@@ -921,7 +811,7 @@ __global__ __launch_bounds__(256) void rr_multi_partial_kernel(RrJobs jobs, int6
   typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
   for (int64_t i = i0; i < i1; i += NB * S) {
     float a[NB][S];
-    // rounds stay inside the zero-padded tail, as in rr_partial_kernel
+    // rounds stay inside the zero-padded tail (chunks start at multiples of 64)
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       if (!jb.A) {
@@ -975,11 +865,9 @@ __global__ void rr_multi_sum_kernel(RrJobs jobs, const float* __restrict__ parti
   float s = 0.f;
 #pragma unroll 8
   for (int k = 0; k < nchunks; ++k) s += p[((int64_t)k * rows + r) * (kRrMaxC + 1) + c];
-  if (c == kRrMaxC) {
-    if (jb.bias) jb.bias[r] = s;
-  } else if (jb.out) {
-    jb.out[(int64_t)r * jb.C + c] = s;
-  }
+  float* o = c == kRrMaxC ? jb.bias + r : (jb.out ? jb.out + (int64_t)r * jb.C + c : nullptr);
+  if (c == kRrMaxC && !jb.bias) return;
+  if (o) *o = jb.accumulate ? *o + s : s;
 }
 
 int64_t rr_multi_job_floats(int rows, int64_t B) { return (int64_t)rr_chunks(B) * rows * (kRrMaxC + 1); }
@@ -1008,10 +896,6 @@ hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B
   return hipGetLastError();
 }
 
-hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(vec_sum_kernel, dim3(1), dim3(256), 0, s, x, n, out);
-  return hipGetLastError();
-}
 
 // Entry (r, f) = sum over workgroups w of part[(r W + f) nparts + w]: one wave
 // per entry, lane l adding workgroups l, l + 64, ... in order, then the 64 lane

@@ -238,19 +238,15 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
 // any launch of up to kWgMaxJobs products over at most B samples needs
 int64_t wgrad_chunk_len(int64_t B, int n, int width, int num_cu);
 int64_t wgrad_partial_floats(int64_t B, int width, int num_cu);
-// For each row r < rows: out[r][c] = sum_i A[r][i] V[c][i] (c < C <= 9, V row stride
-// ldv, V[c] holding at least B entries) and bias[r] = sum_i A[r][i] (out / bias may be
-// NULL), i < B, with A (rows x batch) in the blocked feature-major layout of the
-// training dumps; chunked partial sums in `partial` (rr_chunks(B) * rows * 10 floats)
-// added in a fixed order.
-int rr_chunks(int64_t B);
-hipError_t launch_row_reduce(const void* A, bool a_is_bf16, int rows, int64_t B, const float* V, int64_t ldv, int C,
-                             float* out, float* bias, float* partial, hipStream_t s, bool accumulate = false);
-// Up to kRrMaxJobs such reductions over one batch in one pass (two launches):
-// job j reduces A (rows x batch, blocked layout; NULL: a single row of ones)
-// against V (C <= 9 rows of stride ldv, shared ldv) into out (rows x C) and bias
-// (rows), either NULL; no job accumulates onto another's outputs.  partial needs
+// Row reductions over a batch: for each row r < rows, out[r][c] = sum_i A[r][i] V[c][i]
+// (c < C <= 9, V row stride ldv, V[c] holding at least B entries) and
+// bias[r] = sum_i A[r][i] (out / bias may be NULL), i < B, with A (rows x batch) in
+// the blocked feature-major layout of the training dumps (NULL: a single row of
+// ones); chunked partial sums added in a fixed order.  Up to kRrMaxJobs of them in
+// one pass of two launches, sharing ldv; no job writes another's outputs, and a job
+// with `accumulate` adds to what its outputs hold.  partial needs
 // n * rr_multi_job_floats(max rows, B) floats.
+int rr_chunks(int64_t B);
 constexpr int kRrMaxJobs = 7;
 struct RrJob {
   const void* A;
@@ -259,6 +255,7 @@ struct RrJob {
   int C;
   float* out;
   float* bias;
+  int accumulate;  // 1: add to out / bias instead of overwriting them
 };
 struct RrJobs {
   RrJob job[kRrMaxJobs];
@@ -267,8 +264,6 @@ struct RrJobs {
 int64_t rr_multi_job_floats(int rows, int64_t B);
 hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B, int64_t ldv, float* partial,
                                    hipStream_t s);
-// *out = sum_{i < n} x[i] in a fixed order (one workgroup).
-hipError_t launch_vec_sum(const float* x, int64_t n, float* out, hipStream_t s);
 // Workgroups of a one-shot fused_query launch over ntiles tiles: one per compute
 // unit (each holds one), fewer for small launches.  Training's per-workgroup sums
 // are indexed by it.

@@ -167,11 +167,11 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
   // the loss.  (Single-row V operands ignore the shared row stride ldb.)
   gcdf::RrJobs rj{};
   rj.n = sq ? 7 : 6;
-  rj.job[0] = {G(0), W, tr->dumpV, 9, grad + o.W1, grad + o.b1};
-  for (int l = 0; l < 3; ++l) rj.job[1 + l] = {G(l + 1), W, nullptr, 0, nullptr, grad + o.bl[l]};
-  rj.job[4] = {H(3), W, seed, 1, grad + o.w5, nullptr};
-  rj.job[5] = {nullptr, 1, seed, 1, grad + o.b5, nullptr};
-  if (sq) rj.job[6] = {nullptr, 1, sq, 1, loss, nullptr};
+  rj.job[0] = {G(0), W, tr->dumpV, 9, grad + o.W1, grad + o.b1, 0};
+  for (int l = 0; l < 3; ++l) rj.job[1 + l] = {G(l + 1), W, nullptr, 0, nullptr, grad + o.bl[l], 0};
+  rj.job[4] = {H(3), W, seed, 1, grad + o.w5, nullptr, 0};
+  rj.job[5] = {nullptr, 1, seed, 1, grad + o.b5, nullptr, 0};
+  if (sq) rj.job[6] = {nullptr, 1, sq, 1, loss, nullptr, 0};
   if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(rj, false, B, tr->ldb, tr->partial, s);
   return e;
 }
@@ -392,19 +392,21 @@ gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float
   }
   if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(a, W, gcdf::kFP32, ldb, B, tr->partial, tr->num_cu, s, false);
   if (e == hipSuccess) e = gcdf::launch_wgrad_gemm(b, W, gcdf::kFP32, ldb, B, tr->partial, tr->num_cu, s, true);
-  // 5. input layer: dW_1 = sum zbar_1 v^T + g_1 u^T, db_1 = sum zbar_1; db_l = sum zbar_l
-  float* rp = tr->partial;
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(Zb, false, W, B, tr->dumpV, ldb, 9, grad + o.W1, grad + o.b1, rp, s, false);
-  if (e == hipSuccess) e = gcdf::launch_row_reduce(Gs, false, W, B, u, ldb, 9, grad + o.W1, nullptr, rp, s, true);
-  for (int l = 0; l < 3 && e == hipSuccess; ++l)
-    e = gcdf::launch_row_reduce(Zb + (l + 1) * layer, false, W, B, nullptr, 0, 0, nullptr, grad + o.bl[l], rp, s, false);
-  // 6. output layer: dw_out = sum fbar h_4 + hdot_4, db_out = sum fbar
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(H + 3 * layer, false, W, B, fbar, ldb, 1, grad + o.w5, nullptr, rp, s, false);
-  if (e == hipSuccess)
-    e = gcdf::launch_row_reduce(Hd + 3 * layer, false, W, B, nullptr, 0, 0, nullptr, grad + o.w5, rp, s, true);
-  if (e == hipSuccess) e = gcdf::launch_vec_sum(fbar, B, grad + o.b5, s);
+  // 5. the rest in two passes over the batch (fixed-order row reductions, the second
+  //    adding to the first's outputs): input layer dW_1 = sum zbar_1 v^T + g_1 u^T,
+  //    db_1 = sum zbar_1; db_l = sum zbar_l; output layer dw_out = sum fbar h_4 + hdot_4,
+  //    db_out = sum fbar.  (v and u share the row stride ldb.)
+  gcdf::RrJobs r1{}, r2{};
+  r1.n = 6;
+  r1.job[0] = {Zb, W, tr->dumpV, 9, grad + o.W1, grad + o.b1, 0};
+  for (int l = 0; l < 3; ++l) r1.job[1 + l] = {Zb + (l + 1) * layer, W, nullptr, 0, nullptr, grad + o.bl[l], 0};
+  r1.job[4] = {H + 3 * layer, W, fbar, 1, grad + o.w5, nullptr, 0};
+  r1.job[5] = {nullptr, 1, fbar, 1, grad + o.b5, nullptr, 0};
+  r2.n = 2;
+  r2.job[0] = {Gs, W, u, 9, grad + o.W1, nullptr, 1};
+  r2.job[1] = {Hd + 3 * layer, W, nullptr, 0, nullptr, grad + o.w5, 1};
+  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(r1, false, B, ldb, tr->partial, s);
+  if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(r2, false, B, ldb, tr->partial, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_table1: %s", hipGetErrorString(e));
 }
 
