@@ -511,7 +511,6 @@ struct DumpSums {
   float* row;          // [W]: sum_i x[f][i] w_i
   const float* seed;   // w_i = seed[i * XIN_FLOATS] (the records' seed slot), or NULL: w_i = 1
   float* in_rows;      // [9][W]: sum_i x[f][i] v_c(i), or NULL
-  const float* xin;    // per-query records
   const __bf16* vt;    // the tile's inputs v_c(i) as BF16 hi [9][64], then lo [9][64]
 };
 
@@ -801,7 +800,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
     }
     // h4 is needed only for dL/dw_out = sum_i seed_i h4_i: summed here when the
     // tile engine keeps the bias sums, else written out
-    const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.xin, td.vt};
+    const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.h(3), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
     __syncthreads();  // h4 fully read before g4 overwrites the tile; seeds written
   }
@@ -850,7 +849,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
   // overwritten only after the following K loop and its barrier
   if constexpr (TRAIN) {  // h2, h3, or g4 (with db4 = sum_i g4_i)
-    const DumpSums sm{td.row(3), nullptr, nullptr, td.xin, td.vt};
+    const DumpSums sm{td.row(3), nullptr, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid,
                        (L == 2 && td.bsum) ? &sm : nullptr);
   }
@@ -901,7 +900,7 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   }
   __syncthreads();
   if constexpr (TRAIN) {  // g3 or g2, with their bias sums
-    const DumpSums sm{td.row(L), nullptr, nullptr, td.xin, td.vt};
+    const DumpSums sm{td.row(L), nullptr, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.g(L), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr);
   }
 }
@@ -972,7 +971,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
     __syncthreads();
     // g1 is needed only for db1 and dW1 = sum_i g1_i v_i^T: summed here when the
     // tile engine keeps the sums, else written out
-    const DumpSums sm{td.row(0), nullptr, td.row(5), td.xin, td.vt};
+    const DumpSums sm{td.row(0), nullptr, td.row(5), td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.g(0), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
   }
 }
