@@ -85,9 +85,21 @@ class Trainer:
         gradient in one pass (gcdf_train_mse): (loss float32[1], grad)."""
         import torch
 
+        _check_samples(params, knots, points, self)
         B = knots.shape[0]
+        if target is None:
+            raise ValueError("target is required")
+        for t, name in ((target, "target"), (d, "d")):
+            if t is not None:
+                _checked(t, name)
+                if tuple(t.shape) != (B,) or t.device != params.device:
+                    raise ValueError("%s must be (B,) on the parameters' device" % name)
         if grad is None:
             grad = torch.empty_like(params)
+        elif tuple(grad.shape) != tuple(params.shape):
+            raise ValueError("grad must be shaped like params")
+        else:
+            _checked(grad, "grad")
         loss = torch.empty(1, dtype=torch.float32, device=params.device)
         self._packed = None
         _check(library().gcdf_train_mse(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
@@ -128,6 +140,8 @@ def _check_samples(params, knots, points, trainer):
     _checked(params, "params")
     _checked(knots, "knots")
     _checked(points, "points")
+    if knots.device != params.device or points.device != params.device:
+        raise ValueError("params, knots and points must be on one device")
     B = knots.shape[0]
     if knots.dim() != 2 or knots.shape[1] != 9 or tuple(points.shape) != (B, 3):
         raise ValueError("knots must be (B, 9) and points (B, 3)")
@@ -167,11 +181,7 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, params, knots, points, target, trainer):
-            _check_samples(params, knots, points, trainer)
-            _checked(target, "target")
-            if tuple(target.shape) != (knots.shape[0],):
-                raise ValueError("target must be (B,)")
-            loss, g = trainer.mse(params.detach(), knots, points, target)
+            loss, g = trainer.mse(params.detach(), knots, points, target)  # (checks its arguments)
             ctx.grad = g
             return loss.reshape(())
 
