@@ -140,6 +140,74 @@ def test_fused_mse_agrees_with_forward_then_backward(tr_mod, precision, tol):
     trainer.close()
 
 
+EDGE_B = [1, 63, 64, 65, 64 * 256 + 5]
+
+
+@pytest.mark.parametrize("B", EDGE_B)
+def test_fused_mse_edge_batches_match_oracle(tr_mod, oracle_mod, B):
+    """One sample, a partial tile, exactly one tile, one tile plus one sample, and 257
+    tiles (one more than a round of workgroups on 256 compute units, the last one
+    ragged): in FP32 the loss and every parameter array against the oracle."""
+    w = wl.weights(256, seed=43, bf16_hidden=False)
+    k, p, y = batch(B, 18)
+    print("case fused MSE edge B=%d fp32" % B, flush=True)
+    _, _, _, _, loss, d, g = fused_grads(tr_mod, "fp32", w, k, p, y)
+    loss_ref, gref = oracle_mod.mse_grad(w.to_blob(), k.astype(np.float64), p.astype(np.float64), y)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    for name, a, b in zip(NAMES, split(g, w), gref):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert np.all(np.isfinite(a)) and err <= 1e-5, (name, err)
+
+
+@pytest.mark.parametrize("B", EDGE_B)
+def test_fused_mse_edge_batches_bf16(tr_mod, B):
+    """The same batches in BF16 against the separate BF16 forward + backward (the same
+    arithmetic but for the seeds' rounding).  Against the FP64 oracle the BF16 error
+    of d (~1e-2 with FP32 hidden weights off the BF16 grid) can dominate a small
+    gradient such as db_out = 2 mean(d - y), so the oracle bar of the large batches
+    does not apply at every size."""
+    w = wl.weights(256, seed=43, bf16_hidden=False)
+    k, p, y = batch(B, 18)
+    print("case fused MSE edge B=%d bf16" % B, flush=True)
+    _, _, _, _, d0, g0 = gpu_grads(tr_mod, "bf16", w, k, p, y)
+    _, _, _, _, loss, d, g = fused_grads(tr_mod, "bf16", w, k, p, y)
+    assert np.abs(d - d0).max() <= 1e-6 * max(1.0, np.abs(d0).max())
+    ref = float(np.mean((d0.astype(np.float64) - y) ** 2))
+    assert abs(loss - ref) <= 1e-5 * ref
+    for name, a, b in zip(NAMES, split(g, w), split(g0, w)):
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert np.all(np.isfinite(a)) and err <= 1e-2, (name, err)
+
+
+def test_fused_mse_rejects_bad_arguments(tr_mod):
+    import ctypes
+
+    from paper_2601_18548_amd import EINVAL, library
+
+    w = wl.weights(256, seed=44, bf16_hidden=False)
+    k, p, y = batch(100, 19)
+    trainer = tr_mod.Trainer(256, "bf16", max_batch=100)
+    params = tr_mod.flat_params(w)
+    kt, pt, yt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(y).cuda()
+    loss = torch.empty(1, device="cuda")
+    grad = torch.empty_like(params)
+    lib = library()
+    args = [trainer._h, params.data_ptr(), kt.data_ptr(), pt.data_ptr(), 100, yt.data_ptr(), loss.data_ptr(),
+            grad.data_ptr(), None, None]
+    for i in (5, 6, 7):  # target, loss, grad NULL
+        bad = list(args)
+        bad[i] = None
+        assert lib.gcdf_train_mse(*bad) == EINVAL
+    for b in (0, 101):  # batch outside [1, max_batch]
+        bad = list(args)
+        bad[4] = b
+        assert lib.gcdf_train_mse(*bad) == EINVAL
+    assert lib.gcdf_train_mse(*args) == 0
+    with pytest.raises(ValueError):
+        trainer.mse(params, kt, pt, yt[:50].contiguous())
+    trainer.close()
+
+
 def test_fused_mse_autograd_and_determinism(tr_mod):
     w = wl.weights(256, seed=42, bf16_hidden=False)
     k, p, y = batch(2048 + 37, 17)
