@@ -342,7 +342,7 @@ def train_bench(torch, steps: int, warmup: int, batch: int = 65536, width: int =
     with torch.no_grad():
         y = tr.forward(train.flat_params(teacher), kt, pt) + torch.from_numpy(noise).cuda()
     params = train.flat_params(student).requires_grad_(True)
-    opt = train.adam(params, lr=5e-3, betas=(0.9, 0.999))
+    opt = train.adam(params, lr=5e-3, betas=(0.9, 0.999), trainer=tr)  # Adam packs the next step's weights
     loss0 = None
     for _ in range(warmup):
         loss0 = train.mse_step(params, opt, tr, kt, pt, y)

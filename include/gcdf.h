@@ -326,14 +326,17 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
  * over the samples (knot i, point i), with d the network distance, and its weight
  * gradient, from one training-mode pass (no separate forward).  Each 64-sample
  * tile finishes d before its reverse sweep and seeds the sweep with
- * dL/dd_i = 2 (d_i - y_i) / B; otherwise as gcdf_train_backward (weights packed
- * from params at every call, deterministic).  target: device float32[B];
+ * dL/dd_i = 2 (d_i - y_i) / B; otherwise as gcdf_train_backward (deterministic;
+ * the weights are packed from params unless reuse_packed is 1 and params is the
+ * pointer this trainer last packed or updated with gcdf_train_adam_step, and was
+ * not changed since).  target: device float32[B];
  * loss: device float32[1]; grad_params: device, overwritten; d: device
  * float32[B] for the distances, or NULL.  EINVAL: NULL tr, params, knots,
  * points, target, loss or grad_params, or B outside [1, max_batch].  The
  * trainer's buffers make concurrent calls on one trainer race. */
 gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* knots, const float* points, int64_t B,
-                           const float* target, float* loss, float* grad_params, float* d, void* stream);
+                           const float* target, float* loss, float* grad_params, float* d, int32_t reuse_packed,
+                           void* stream);
 
 /* The training loss of Table I (Sec. III-C) over the samples (knot i, point i)
  * and its weight gradient.  With F the network distance and J = dF/dq the
@@ -351,6 +354,14 @@ gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* k
 gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float* knots, const float* points,
                               int64_t B, const float* fstar, const float* Jstar, const float* m_diag,
                               const float* lambda, float* losses, float* grad_params, void* stream);
+
+/* gcdf_adam_step over a trainer's flat parameter vector (gcdf_param_count(width)
+ * floats; grad, m and v in the same layout) that also packs the updated weights
+ * into the trainer, in one launch, so that the next gcdf_train_mse or
+ * gcdf_train_backward with reuse_packed = 1 and the same params pointer needs no
+ * packing.  Same arithmetic and EINVAL cases as gcdf_adam_step (NULL tr too). */
+gcdf_status gcdf_train_adam_step(gcdf_trainer* tr, float* params, const float* grad, float* m, float* v, float lr,
+                                 float beta1, float beta2, float eps, int64_t step, void* stream);
 
 /* One Adam step (the optimiser of the paper's training, Sec. V-A) over n device
  * floats, in torch.optim.Adam's arithmetic (no weight decay, no amsgrad):

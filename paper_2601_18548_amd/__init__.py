@@ -80,10 +80,13 @@ def library() -> ctypes.CDLL:
     lib.gcdf_train_forward.restype = ctypes.c_int
     lib.gcdf_train_backward.argtypes = [P, P, P, P, I64, P, P, ctypes.c_int32, P]
     lib.gcdf_train_backward.restype = ctypes.c_int
-    lib.gcdf_train_mse.argtypes = [P, P, P, P, I64, P, P, P, P, P]
+    lib.gcdf_train_mse.argtypes = [P, P, P, P, I64, P, P, P, P, ctypes.c_int32, P]
     lib.gcdf_train_mse.restype = ctypes.c_int
     lib.gcdf_train_table1.argtypes = [P, P, P, P, I64, P, P, P, P, P, P, P]
     lib.gcdf_train_table1.restype = ctypes.c_int
+    lib.gcdf_train_adam_step.argtypes = [P, P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, I64, P]
+    lib.gcdf_train_adam_step.restype = ctypes.c_int
     lib.gcdf_adam_step.argtypes = [P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    I64, P]
     lib.gcdf_adam_step.restype = ctypes.c_int
@@ -112,7 +115,8 @@ EXPORTED = ["gcdf_create", "gcdf_destroy", "gcdf_last_error", "gcdf_eval", "gcdf
             "gcdf_knot_min", "gcdf_query", "gcdf_query_noalloc", "gcdf_submit", "gcdf_poll", "gcdf_param_count",
             "gcdf_trainer_create", "gcdf_trainer_destroy", "gcdf_train_forward", "gcdf_train_backward",
             "gcdf_partition_count", "gcdf_partition_fill", "gcdf_eval_grad_csr", "gcdf_jacobian_pattern",
-            "gcdf_project", "gcdf_project_csr", "gcdf_adam_step", "gcdf_train_table1", "gcdf_train_mse"]
+            "gcdf_project", "gcdf_project_csr", "gcdf_adam_step", "gcdf_train_table1", "gcdf_train_mse",
+            "gcdf_train_adam_step"]
 
 
 def _check(st: int, ctx=None):

@@ -524,6 +524,97 @@ __global__ __launch_bounds__(256) void pack_all_kernel(PackJob pj) {
   }
 }
 
+// Index of element (row, col) in a packed matrix (the inverse of pack_bf16_elem
+// with the natural K order, resp. pack_fp32_elem, without transposition).
+__device__ __forceinline__ int64_t packed_index_bf16(int row, int col, int W) {
+  const int MT = W / (32 * kWaves), NKB = W / 16;
+  const int wave = row / (32 * MT), i = (row / 32) % MT;
+  const int kb = col / 16, lane = row % 32 + 32 * ((col % 16) / 8), e = col % 8;
+  return ((((int64_t)wave * NKB + kb) * MT + i) * 64 + lane) * 8 + e;
+}
+__device__ __forceinline__ int64_t packed_index_fp32(int row, int col, int W) {
+  const int MT = W / (32 * kWaves), NK8 = W / 8;
+  const int wave = row / (32 * MT), i = (row / 32) % MT;
+  const int j = col / 8, lane = row % 32 + 32 * (col % 2), q = (col % 8) / 2;
+  return ((((int64_t)wave * NK8 + j) * MT + i) * 64 + lane) * 4 + q;
+}
+
+// Adam over a network's flat parameters, every updated value also packed: grid y
+// = 0..2 the hidden matrices (threads in the forward packing's order, each writing
+// its element to the forward and the transposed packing), 3 the row vectors b2,
+// b3, b4, w_out, 4 the input layer (row r: W1[r][:], b1[r]; thread 0 also b_out).
+__global__ __launch_bounds__(256) void adam_pack_kernel(PackJob pj, float* __restrict__ p, const float* __restrict__ g,
+                                                        float* __restrict__ m, float* __restrict__ v, int64_t b5_off,
+                                                        AdamConsts a) {
+  const int W = pj.width;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (y < 3) {
+    if (idx >= (int64_t)W * W) return;
+    const int lane = pj.mode == kFP32 ? (int)((idx >> 2) & 63) : (int)((idx >> 3) & 63);
+    int row, col;
+    {
+      const int MT = W / (32 * kWaves);
+      if (pj.mode == kFP32) {
+        const int q = (int)(idx & 3);
+        int64_t chunk = idx >> 8;
+        const int i = (int)(chunk % MT);
+        chunk /= MT;
+        const int j = (int)(chunk % (W / 8)), wave = (int)(chunk / (W / 8));
+        row = 32 * (wave * MT + i) + (lane & 31);
+        col = 8 * j + 2 * q + (lane >> 5);
+      } else {
+        const int e = (int)(idx & 7);
+        int64_t chunk = idx >> 9;
+        const int i = (int)(chunk % MT);
+        chunk /= MT;
+        const int kb = (int)(chunk % (W / 16)), wave = (int)(chunk / (W / 16));
+        row = 32 * (wave * MT + i) + (lane & 31);
+        col = 16 * kb + 8 * (lane >> 5) + e;
+      }
+    }
+    const float pn = adam_update(p, g, m, v, (pj.Wl[y] - p) + (int64_t)row * W + col, a);
+    if (pj.mode == kFP32) {
+      static_cast<float*>(pj.fwd[y])[idx] = pn;
+      static_cast<float*>(pj.bwd[y])[packed_index_fp32(col, row, W)] = pn;
+    } else {
+      const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pn);
+      static_cast<uint16_t*>(pj.fwd[y])[idx] = b;
+      static_cast<uint16_t*>(pj.bwd[y])[packed_index_bf16(col, row, W)] = b;
+    }
+  } else if (y == 3) {
+    if (idx >= 4 * (int64_t)W) return;
+    const int vi = (int)(idx / W), r = (int)(idx % W);
+    const float* src = vi < 3 ? pj.bl[vi] : pj.w5;
+    float* dst = vi < 3 ? pj.bh + (size_t)vi * W : pj.w5p;
+    dst[lane_major_pos(r, W)] = adam_update(p, g, m, v, (src - p) + r, a);
+  } else {
+    if (idx >= W) return;
+    const int r = (int)idx;
+    const int64_t w0 = (pj.W1 - p) + (int64_t)r * kInDim;
+    float w[kInDim];
+#pragma unroll
+    for (int c = 0; c < kInDim; ++c) w[c] = adam_update(p, g, m, v, w0 + c, a);
+    float* o = pj.w1p + lane_major_pos(r, W) * 12;
+    o[0] = w[0];
+    o[1] = w[1];
+    o[2] = w[2];
+    o[3] = adam_update(p, g, m, v, (pj.b1 - p) + r, a);
+    for (int c = 0; c < 6; ++c) o[4 + c] = w[3 + c];
+    o[10] = 0.f;
+    o[11] = 0.f;
+    if (r == 0) adam_update(p, g, m, v, b5_off, a);
+  }
+}
+
+hipError_t launch_adam_pack(const PackJob& pj, float* params, const float* grad, float* m, float* v,
+                            const AdamConsts& a, int64_t b5_off, hipStream_t s) {
+  if (pj.in_dim != kInDim || (pj.mode != kFP32 && pj.mode != kBF16)) return hipErrorInvalidValue;
+  const unsigned bx = (unsigned)(((int64_t)pj.width * pj.width + 255) / 256);
+  hipLaunchKernelGGL(adam_pack_kernel, dim3(bx, 5), dim3(256), 0, s, pj, params, grad, m, v, b5_off, a);
+  return hipGetLastError();
+}
+
 hipError_t pack_network(const PackJob& pj, hipStream_t s) {
   if (pj.in_dim != kInDim && pj.in_dim != kInDimSphere) return hipErrorInvalidValue;
   const unsigned bx = (unsigned)(((int64_t)pj.width * pj.width + 255) / 256);

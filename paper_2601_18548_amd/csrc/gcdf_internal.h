@@ -313,4 +313,29 @@ hipError_t launch_table1_loss(const float* knots, const float* points, const flo
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t s);
 
+// One Adam update of element i in torch.optim.Adam's operation order (no weight
+// decay, no amsgrad); lr_corr = lr / (1 - b1^t), inv_sqrt_bc2 = 1 / sqrt(1 - b2^t).
+struct AdamConsts {
+  float lr_corr, b1, b2, inv_sqrt_bc2, eps;
+  static AdamConsts make(float lr, float b1, float b2, float eps, int64_t step);
+};
+__device__ __forceinline__ float adam_update(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                             float* __restrict__ v, int64_t i, const AdamConsts& a) {
+  const float gi = g[i];
+  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float denom = sqrtf(vi) * a.inv_sqrt_bc2 + a.eps;
+  const float pi = p[i] - a.lr_corr * (mi / denom);
+  p[i] = pi;
+  return pi;
+}
+// Adam over the flat parameters of a point network (pj's source pointers point into
+// params; grad, m, v share its layout; b_out at params[b5_off]) with every updated
+// value also written to pj's packed arrays, in one launch, so the packing of the
+// next forward is done.  FP32 and pure-BF16 packings (the training precisions).
+hipError_t launch_adam_pack(const PackJob& pj, float* params, const float* grad, float* m, float* v,
+                            const AdamConsts& a, int64_t b5_off, hipStream_t s);
+
 }  // namespace gcdf

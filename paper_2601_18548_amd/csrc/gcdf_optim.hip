@@ -17,27 +17,24 @@ namespace gcdf {
 namespace {
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t n, float lr_corr, float b1, float b2, float inv_sqrt_bc2,
-                            float eps) {
+                            float* __restrict__ v, int64_t n, AdamConsts a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float denom = sqrtf(vi) * inv_sqrt_bc2 + eps;
-  p[i] = p[i] - lr_corr * (mi / denom);
+  adam_update(p, g, m, v, i, a);
 }
 
 }  // namespace
 
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                       float eps, int64_t step, hipStream_t s) {
+AdamConsts AdamConsts::make(float lr, float b1, float b2, float eps, int64_t step) {
   const double bc1 = 1.0 - std::pow((double)b1, (double)step);
   const double bc2 = 1.0 - std::pow((double)b2, (double)step);
+  return AdamConsts{(float)(lr / bc1), b1, b2, (float)(1.0 / std::sqrt(bc2)), eps};
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int64_t step, hipStream_t s) {
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n,
-                     (float)(lr / bc1), b1, b2, (float)(1.0 / std::sqrt(bc2)), eps);
+                     AdamConsts::make(lr, b1, b2, eps, step));
   return hipGetLastError();
 }
 

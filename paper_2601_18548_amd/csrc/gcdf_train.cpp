@@ -76,7 +76,8 @@ struct DevGuard {
   }
 };
 
-hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
+// The packing of params into the trainer's packed arrays.
+gcdf::PackJob pack_job(const gcdf_trainer* tr, const float* params) {
   const Offsets o(tr->W);
   char* base = static_cast<char*>(tr->wbuf);
   gcdf::PackJob pj{};
@@ -95,8 +96,12 @@ hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
   pj.bh = const_cast<float*>(tr->net.bh);
   pj.w5p = const_cast<float*>(tr->net.w5);
   pj.w1p = const_cast<float*>(tr->net.w1p);
-  hipError_t e = gcdf::pack_network(pj, s);
-  tr->net.b5p = params + o.b5;
+  return pj;
+}
+
+hipError_t pack(gcdf_trainer* tr, const float* params, hipStream_t s) {
+  hipError_t e = gcdf::pack_network(pack_job(tr, params), s);
+  tr->net.b5p = params + Offsets(tr->W).b5;
   tr->packed_from = e == hipSuccess ? params : nullptr;
   return e;
 }
@@ -285,13 +290,14 @@ gcdf_status gcdf_train_backward(gcdf_trainer* tr, const float* params, const flo
 }
 
 gcdf_status gcdf_train_mse(gcdf_trainer* tr, const float* params, const float* knots, const float* points, int64_t B,
-                           const float* target, float* loss, float* grad, float* d, void* stream) {
+                           const float* target, float* loss, float* grad, float* d, int32_t reuse_packed,
+                           void* stream) {
   gcdf_status st = check(tr, params, knots, points, B);
   if (st != GCDF_OK) return st;
   if (!target || !loss || !grad) return tfail(GCDF_EINVAL, "target, loss or grad_params is NULL");
   DevGuard g(tr->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = pack(tr, params, s);
+  hipError_t e = (reuse_packed && tr->packed_from == params) ? hipSuccess : pack(tr, params, s);
   gcdf::Job job = training_job(tr, knots, points, B);
   float* seed = tr->mse;
   float* sq = tr->mse + tr->ldb;
@@ -408,6 +414,22 @@ gcdf_status gcdf_train_table1(gcdf_trainer* tr, const float* params, const float
   if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(r1, false, B, ldb, tr->partial, s);
   if (e == hipSuccess) e = gcdf::launch_row_reduce_multi(r2, false, B, ldb, tr->partial, s);
   return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_table1: %s", hipGetErrorString(e));
+}
+
+gcdf_status gcdf_train_adam_step(gcdf_trainer* tr, float* params, const float* grad, float* m, float* v, float lr,
+                                 float beta1, float beta2, float eps, int64_t step, void* stream) {
+  if (!tr || !params || !grad || !m || !v) return tfail(GCDF_EINVAL, "NULL pointer to gcdf_train_adam_step");
+  if (step < 1) return tfail(GCDF_EINVAL, "step must be >= 1");
+  if (!std::isfinite(lr) || !std::isfinite(eps) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return tfail(GCDF_EINVAL, "lr / eps must be finite and betas in [0, 1)");
+  DevGuard g(tr->device);
+  const Offsets o(tr->W);
+  const hipError_t e = gcdf::launch_adam_pack(pack_job(tr, params), params, grad, m, v,
+                                              gcdf::AdamConsts::make(lr, beta1, beta2, eps, step), (int64_t)o.b5,
+                                              static_cast<hipStream_t>(stream));
+  tr->net.b5p = params + o.b5;
+  tr->packed_from = e == hipSuccess ? params : nullptr;
+  return e == hipSuccess ? GCDF_OK : tfail(GCDF_EDEVICE, "gcdf_train_adam_step: %s", hipGetErrorString(e));
 }
 
 gcdf_status gcdf_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,

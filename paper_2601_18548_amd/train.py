@@ -59,9 +59,12 @@ class Trainer:
         return d
 
     def packed_is_current(self, params) -> bool:
-        """True if the library's packed weights were made from `params` as it is now."""
+        """True if the library's packed weights were made from `params` as it is now:
+        the same storage (a detached alias shares it and its version counter) at the
+        same version."""
         pk = getattr(self, "_packed", None)
-        return pk is not None and pk[0] is params and pk[1] == params._version
+        return (pk is not None and pk[0].data_ptr() == params.data_ptr() and pk[1] == params._version
+                and pk[0]._version == pk[1])
 
     def backward(self, params, knots, points, grad_d, grad=None, reuse_packed: bool = False, stream=None):
         """reuse_packed: params is unchanged since the last forward/backward call
@@ -80,9 +83,11 @@ class Trainer:
         return grad
 
 
-    def mse(self, params, knots, points, target, grad=None, d=None, stream=None):
+    def mse(self, params, knots, points, target, grad=None, d=None, reuse_packed: bool = False, stream=None):
         """Mean squared error of the network distances against target and its weight
-        gradient in one pass (gcdf_train_mse): (loss float32[1], grad)."""
+        gradient in one pass (gcdf_train_mse): (loss float32[1], grad).
+        reuse_packed: params is unchanged since this trainer last packed it (a forward,
+        backward or mse call, or an Adam step with this trainer)."""
         import torch
 
         _check_samples(params, knots, points, self)
@@ -101,10 +106,12 @@ class Trainer:
         else:
             _checked(grad, "grad")
         loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        reuse = bool(reuse_packed) and self.packed_is_current(params)
         self._packed = None
         _check(library().gcdf_train_mse(self._h, params.data_ptr(), knots.data_ptr(), points.data_ptr(), B,
                                         target.data_ptr(), loss.data_ptr(), grad.data_ptr(),
-                                        d.data_ptr() if d is not None else None, _stream(stream)))
+                                        d.data_ptr() if d is not None else None, 1 if reuse else 0,
+                                        _stream(stream)))
         self._packed = (params, params._version)
         return loss, grad
 
@@ -181,14 +188,19 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, params, knots, points, target, trainer):
-            loss, g = trainer.mse(params.detach(), knots, points, target)  # (checks its arguments)
+            # (Trainer.mse checks its arguments, and packs the weights unless this trainer's
+            # last packing, e.g. by its Adam step, is of these unchanged parameters)
+            loss, g = trainer.mse(params.detach(), knots, points, target, reuse_packed=True)
             ctx.grad = g
             return loss.reshape(())
 
         @staticmethod
         def backward(ctx, grad_loss):
-            g = ctx.grad.mul_(grad_loss)
+            g = ctx.grad
             ctx.grad = None
+            # the step's own unit seed (a cached 1.0 that nothing writes) needs no scaling
+            if grad_loss.data_ptr() != _unit(grad_loss.device).data_ptr():
+                g.mul_(grad_loss)
             return g, None, None, None, None
 
     return GcdfNet, GcdfMSE
@@ -220,11 +232,16 @@ class Adam:
     (gcdf_adam_step: torch.optim.Adam's arithmetic, one launch over the whole
     vector).  Minimal optimiser interface: zero_grad(), step()."""
 
-    def __init__(self, params, lr: float = 5e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+    def __init__(self, params, lr: float = 5e-3, betas=(0.9, 0.999), eps: float = 1e-8, trainer=None):
         import torch
 
         if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()):
             raise ValueError("params must be a contiguous float32 CUDA tensor")
+        if trainer is not None and params.numel() != param_count(trainer.width):
+            raise ValueError("params must hold the trainer's %d floats" % param_count(trainer.width))
+        # with a trainer, each step also packs the updated weights into it
+        # (gcdf_train_adam_step), so its next loss call skips the packing
+        self.trainer = trainer
         self.params, self.lr, self.betas, self.eps = params, float(lr), (float(betas[0]), float(betas[1])), float(eps)
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
@@ -243,18 +260,42 @@ class Adam:
             return
         self.t += 1
         p = self.params.detach()
-        _check(library().gcdf_adam_step(p.data_ptr(), g.contiguous().data_ptr(), self.m.data_ptr(),
-                                        self.v.data_ptr(), p.numel(), self.lr, self.betas[0], self.betas[1],
-                                        self.eps, self.t, _stream(stream)))
+        g = g.contiguous()
+        tr = self.trainer
+        if tr is not None:
+            tr._packed = None
+            _check(library().gcdf_train_adam_step(tr._h, p.data_ptr(), g.data_ptr(), self.m.data_ptr(),
+                                                  self.v.data_ptr(), self.lr, self.betas[0], self.betas[1],
+                                                  self.eps, self.t, _stream(stream)))
+        else:
+            _check(library().gcdf_adam_step(p.data_ptr(), g.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                            p.numel(), self.lr, self.betas[0], self.betas[1], self.eps, self.t,
+                                            _stream(stream)))
         # the kernel wrote the parameters in place: let torch (and Trainer's packed-weight
         # check) see a new version
         import torch
 
         torch.autograd.graph.increment_version(self.params)
+        if tr is not None:
+            tr._packed = (self.params, self.params._version)
 
 
-def adam(params, lr: float = 5e-3, betas=(0.9, 0.999)):
-    return Adam(params, lr=lr, betas=betas)
+def adam(params, lr: float = 5e-3, betas=(0.9, 0.999), trainer=None):
+    return Adam(params, lr=lr, betas=betas, trainer=trainer)
+
+
+_UNIT = {}
+
+
+def _unit(device):
+    """A cached device scalar 1.0 per device (never written), the upstream gradient
+    mse_step hands to backward instead of the one loss.backward() would fill."""
+    import torch
+
+    t = _UNIT.get(device)
+    if t is None:
+        t = _UNIT[device] = torch.ones((), dtype=torch.float32, device=device)
+    return t
 
 
 def mse_step(params, opt, trainer, knots, points, targets):
@@ -262,6 +303,6 @@ def mse_step(params, opt, trainer, knots, points, targets):
     optimiser step."""
     opt.zero_grad(set_to_none=True)
     loss = gcdf_mse(params, knots, points, targets, trainer)
-    loss.backward()
+    loss.backward(_unit(loss.device))
     opt.step()
     return loss

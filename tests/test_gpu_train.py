@@ -193,7 +193,7 @@ def test_fused_mse_rejects_bad_arguments(tr_mod):
     grad = torch.empty_like(params)
     lib = library()
     args = [trainer._h, params.data_ptr(), kt.data_ptr(), pt.data_ptr(), 100, yt.data_ptr(), loss.data_ptr(),
-            grad.data_ptr(), None, None]
+            grad.data_ptr(), None, 0, None]
     for i in (5, 6, 7):  # target, loss, grad NULL
         bad = list(args)
         bad[i] = None
@@ -322,6 +322,44 @@ def test_native_adam_matches_torch_adam(tr_mod):
     # each step moves a parameter by at most ~lr; FP32 rounding of the update
     assert np.abs(got - want).max() <= 1e-5
     assert np.abs(got - p0).max() > 1e-2  # it did move
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_adam_step_with_trainer_packs_what_a_fresh_packing_gives(tr_mod, precision):
+    """gcdf_train_adam_step: the parameters and moments bitwise equal to
+    gcdf_adam_step's, and the loss and gradient of the next call, which reuses the
+    packing it wrote, bitwise equal to a fresh trainer's (which packs the updated
+    parameters itself); then three mse_step steps with and without the trainer in the
+    optimiser give the same parameters."""
+    w = wl.weights(256, seed=45, bf16_hidden=False)
+    k, p, y = batch(1000, 20)
+    kt, pt, yt = torch.from_numpy(k).cuda(), torch.from_numpy(p).cuda(), torch.from_numpy(y).cuda()
+    trainer = tr_mod.Trainer(256, precision, max_batch=1000)
+    a = tr_mod.flat_params(w)
+    b = a.clone()
+    _, g = trainer.mse(a, kt, pt, yt)
+    g = g.clone()
+    oa = tr_mod.Adam(a, lr=5e-3, trainer=trainer)
+    ob = tr_mod.Adam(b, lr=5e-3)
+    a.grad, b.grad = g, g.clone()
+    oa.step()
+    ob.step()
+    assert torch.equal(a, b) and torch.equal(oa.m, ob.m) and torch.equal(oa.v, ob.v)
+    assert trainer.packed_is_current(a)
+    l1, g1 = trainer.mse(a, kt, pt, yt, reuse_packed=True)
+    fresh = tr_mod.Trainer(256, precision, max_batch=1000)
+    l2, g2 = fresh.mse(b, kt, pt, yt)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    # whole steps through the autograd function
+    pa = tr_mod.flat_params(w).requires_grad_(True)
+    pb = tr_mod.flat_params(w).requires_grad_(True)
+    sa, sb = tr_mod.adam(pa, trainer=trainer), tr_mod.adam(pb)
+    for _ in range(3):
+        tr_mod.mse_step(pa, sa, trainer, kt, pt, yt)
+        tr_mod.mse_step(pb, sb, fresh, kt, pt, yt)
+    assert torch.equal(pa, pb)
+    trainer.close()
+    fresh.close()
 
 
 def test_packed_weights_reused_only_when_unchanged(tr_mod):
