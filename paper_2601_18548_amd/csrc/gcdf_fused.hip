@@ -826,10 +826,33 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
       }
 }
 
-// out_j[e] = sum over chunks (in index order) of partial[j][chunk][e], 4 elements per thread.
-__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs, int accum) {
-  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+// Entry (r, f) = sum over workgroups w of part[(r W + f) nparts + w]: one wave
+// per entry, lane l adding workgroups l, l + 64, ... in order, then the 64 lane
+// sums in a fixed butterfly (the result does not depend on scheduling).
+__device__ __forceinline__ void part_sum_entry(const PartSum& ps, int j, int lane) {
+  const int W = ps.width;
+  if (j >= kTrainSumRows * W) return;
+  const int r = j / W, f = j % W;
+  if (!ps.out.base[r] || f >= ps.out.n[r]) return;
+  const float* p = ps.part + (int64_t)j * ps.nparts;
+  float s = 0.f;
+  for (int w = lane; w < ps.nparts; w += 64) s += p[w];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) ps.out.base[r][(int64_t)f * ps.out.stride[r]] = s;
+}
+
+// out_j[e] = sum over chunks (in index order) of partial[j][chunk][e], 4 elements per
+// thread; blockIdx.y == jobs.n: the training kernel's per-workgroup sums (PartSum),
+// one wave per entry.
+__global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs, int accum,
+                                  PartSum ps) {
   const int job = blockIdx.y;
+  if (job == jobs.n) {
+    part_sum_entry(ps, blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6), threadIdx.x & 63);
+    return;
+  }
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (t >= n) return;
   const float* p = partial + (int64_t)job * nchunks * n + t;
   f32x4 s = {0.f, 0.f, 0.f, 0.f};
@@ -844,8 +867,9 @@ __global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks
 }
 
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int num_cu, hipStream_t s, bool accumulate) {
+                             int num_cu, hipStream_t s, bool accumulate, const PartSum* ps) {
   if (jobs.n < 1 || jobs.n > kWgMaxJobs || width % 128 || B <= 0) return hipErrorInvalidValue;
+  if (ps && (ps->nparts < 1 || ps->width < 1)) return hipErrorInvalidValue;
   const int64_t chunk_len = wgrad_chunk_len(B, jobs.n, width, num_cu);
   const int nchunks = (int)((B + chunk_len - 1) / chunk_len);
   const int ntile = (width / 128) * (width / 128);
@@ -861,8 +885,10 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)width * width;
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)((n / 4 + 255) / 256), (unsigned)jobs.n), dim3(256), 0, s,
-                     partial, nchunks, n, jobs, accumulate ? 1 : 0);
+  const unsigned bx = (unsigned)((n / 4 + 255) / 256);
+  const unsigned bps = ps ? (unsigned)((kTrainSumRows * ps->width + 3) / 4) : 0u;  // 4 entries per block
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(bx > bps ? bx : bps, (unsigned)jobs.n + (ps ? 1u : 0u)), dim3(256), 0, s,
+                     partial, nchunks, n, jobs, accumulate ? 1 : 0, ps ? *ps : PartSum{});
   return hipGetLastError();
 }
 
@@ -987,29 +1013,5 @@ hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B
   return hipGetLastError();
 }
 
-
-// Entry (r, f) = sum over workgroups w of part[(r W + f) nparts + w]: one wave
-// per entry, lane l adding workgroups l, l + 64, ... in order, then the 64 lane
-// sums in a fixed butterfly (the result does not depend on scheduling).
-__global__ void part_sum_kernel(const float* __restrict__ part, int nparts, int W, PartOut out) {
-  const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= kTrainSumRows * W) return;
-  const int r = j / W, f = j % W;
-  if (!out.base[r] || f >= out.n[r]) return;
-  const float* p = part + (int64_t)j * nparts;
-  float s = 0.f;
-  for (int w = lane; w < nparts; w += 64) s += p[w];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) out.base[r][(int64_t)f * out.stride[r]] = s;
-}
-
-hipError_t launch_part_sum(const float* part, int nparts, int width, const PartOut& out, hipStream_t s) {
-  if (nparts < 1 || width < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(part_sum_kernel, dim3((unsigned)((kTrainSumRows * width + 3) / 4)), dim3(256), 0, s, part, nparts,
-                     width, out);
-  return hipGetLastError();
-}
 
 }  // namespace gcdf

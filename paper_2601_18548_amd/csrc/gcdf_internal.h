@@ -232,8 +232,22 @@ struct WgradJobs {
   float* out[kWgMaxJobs];
   int n;
 };
+// The training kernel's per-workgroup sums (Job::bias_part, nparts workgroups)
+// added in a fixed order: entry f < n[r] of row r goes to base[r][f * stride[r]]
+// (rows with a NULL base are dropped).
+struct PartOut {
+  float* base[kTrainSumRows];
+  int stride[kTrainSumRows];
+  int n[kTrainSumRows];
+};
+struct PartSum {
+  const float* part;
+  int nparts, width;
+  PartOut out;
+};
+// ps (optional): those sums too, in the launch that adds the chunks.
 hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t ldb, int64_t B, float* partial,
-                             int num_cu, hipStream_t s, bool accumulate = false);
+                             int num_cu, hipStream_t s, bool accumulate = false, const PartSum* ps = nullptr);
 // samples per chunk (a multiple of 64) for n products, and the floats of `partial`
 // any launch of up to kWgMaxJobs products over at most B samples needs
 int64_t wgrad_chunk_len(int64_t B, int n, int width, int num_cu);
@@ -268,15 +282,7 @@ hipError_t launch_row_reduce_multi(const RrJobs& jobs, bool a_is_bf16, int64_t B
 // unit (each holds one), fewer for small launches.  Training's per-workgroup sums
 // are indexed by it.
 inline int fused_grid(int64_t ntiles, int num_cu) { return (int)(ntiles < num_cu ? ntiles : num_cu); }
-// The training kernel's per-workgroup sums (Job::bias_part, nparts workgroups)
-// added in a fixed order: entry f < n[r] of row r goes to base[r][f * stride[r]]
-// (rows with a NULL base are dropped).
-struct PartOut {
-  float* base[kTrainSumRows];
-  int stride[kTrainSumRows];
-  int n[kTrainSumRows];
-};
-hipError_t launch_part_sum(const float* part, int nparts, int width, const PartOut& out, hipStream_t s);
+
 
 // Table I training loss (width 256, FP32): per 64-sample tile, the forward, the
 // reverse sweep for e = dF/dv, the tangent pass along u and the reverse mode through

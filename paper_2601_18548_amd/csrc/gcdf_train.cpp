@@ -152,20 +152,23 @@ hipError_t weight_gradients(gcdf_trainer* tr, int64_t B, const float* seed, cons
     wj.H[l] = H(l);
     wj.out[l] = grad + o.Wl[l];
   }
-  hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, tr->num_cu, s);
   const int64_t ntiles = (B + gcdf::kTileQ - 1) / gcdf::kTileQ;
   if (bf) {
-    // everything else was summed per workgroup by the training kernel: add the
-    // workgroups' sums (bias gradients, dw_out, dW1 column by column, db_out, loss)
-    gcdf::PartOut po{};
+    // everything else was summed per workgroup by the training kernel: the launch
+    // that adds the GEMMs' chunks also adds the workgroups' sums (bias gradients,
+    // dw_out, dW1 column by column, db_out, loss)
+    gcdf::PartSum ps{};
+    ps.part = tr->bias_part;
+    ps.nparts = gcdf::fused_grid(ntiles, tr->num_cu);
+    ps.width = W;
     float* rows[5] = {grad + o.b1, grad + o.bl[0], grad + o.bl[1], grad + o.bl[2], grad + o.w5};
-    for (int r = 0; r < 5; ++r) po.base[r] = rows[r], po.stride[r] = 1, po.n[r] = W;
-    for (int c = 0; c < 9; ++c) po.base[5 + c] = grad + o.W1 + c, po.stride[5 + c] = 9, po.n[5 + c] = W;
-    po.base[14] = grad + o.b5, po.stride[14] = 1, po.n[14] = 1;
-    po.base[15] = loss, po.stride[15] = 1, po.n[15] = 1;
-    if (e == hipSuccess) e = gcdf::launch_part_sum(tr->bias_part, gcdf::fused_grid(ntiles, tr->num_cu), W, po, s);
-    return e;
+    for (int r = 0; r < 5; ++r) ps.out.base[r] = rows[r], ps.out.stride[r] = 1, ps.out.n[r] = W;
+    for (int c = 0; c < 9; ++c) ps.out.base[5 + c] = grad + o.W1 + c, ps.out.stride[5 + c] = 9, ps.out.n[5 + c] = W;
+    ps.out.base[14] = grad + o.b5, ps.out.stride[14] = 1, ps.out.n[14] = 1;
+    ps.out.base[15] = loss, ps.out.stride[15] = 1, ps.out.n[15] = 1;
+    return gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, tr->num_cu, s, false, &ps);
   }
+  hipError_t e = gcdf::launch_wgrad_gemm(wj, W, gmode, tr->ldb, B, tr->partial, tr->num_cu, s);
   // FP32: one pass over the batch for the rest (the partial buffer is free again:
   // this follows the GEMMs' chunk sum on the stream): input layer dW1 = G_1 V^T and
   // db1 = sum G_1; db_l = sum G_l; output layer dw_out = H_4 seed, db_out = sum seed;
