@@ -626,7 +626,7 @@ def main():
         out["sphere"] = sphere_bench(g, torch, kernel_ms)
         print("bench: sphere %s" % json.dumps(out["sphere"]), file=sys.stderr, flush=True)
     if args.train_steps > 0:
-        out["training"] = train_bench(torch, args.train_steps, 3, cpu=not args.no_cpu_baseline)
+        out["training"] = train_bench(torch, args.train_steps, 20, cpu=not args.no_cpu_baseline)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
     if args.train_steps > 0:
         out["training_table1"] = table1_bench(g, torch, max(5, args.train_steps // 4), 2)

@@ -539,56 +539,72 @@ __device__ __forceinline__ int64_t packed_index_fp32(int row, int col, int W) {
   return ((((int64_t)wave * NK8 + j) * MT + i) * 64 + lane) * 4 + q;
 }
 
-// Adam over a network's flat parameters, every updated value also packed: grid y
-// = 0..2 the hidden matrices (threads in the forward packing's order, each writing
-// its element to the forward and the transposed packing), 3 the row vectors b2,
-// b3, b4, w_out, 4 the input layer (row r: W1[r][:], b1[r]; thread 0 also b_out).
+// Adam over a network's flat parameters, every updated value also packed.  Blocks
+// [0, 3 T) take the 32 x 32 tiles of the hidden matrices (T per matrix): p, g, m
+// and v are read and written by rows (a wave covers two 128-byte rows), the new
+// values go through LDS, and each packed block the tile covers (32 rows by 16
+// BF16 or 8 FP32 columns, 1 KiB) is written in its own order, for the forward
+// packing and for the transposed one.  Then the row vectors b2, b3, b4, w_out
+// (256 per block) and the input layer (row r: W1[r][:], b1[r]; thread 0 also b_out).
+template <int MODE>
+__device__ __forceinline__ void adam_pack_tile(const PackJob& pj, float* __restrict__ p, const float* __restrict__ g,
+                                               float* __restrict__ m, float* __restrict__ v, const AdamConsts& a,
+                                               int y, int tile) {
+  __shared__ float t_new[32][33];
+  const int W = pj.width, tpr = W / 32;
+  const int r0 = (tile / tpr) * 32, c0 = (tile % tpr) * 32;
+  const int64_t base = (pj.Wl[y] - p) + (int64_t)r0 * W + c0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + 256 * k, r = e >> 5, c = e & 31;
+    t_new[r][c] = adam_update(p, g, m, v, base + (int64_t)r * W + c, a);
+  }
+  __syncthreads();
+  // packed position q of a block -> (row, col) inside the block
+  constexpr int kCols = MODE == kFP32 ? 8 : 16, kPer = 32 * kCols;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int P = threadIdx.x + 256 * k, blk = P / kPer, q = P % kPer;
+    int r, c;
+    if constexpr (MODE == kFP32) {
+      const int ln = q >> 2;
+      r = ln & 31;
+      c = blk * kCols + 2 * (q & 3) + (ln >> 5);
+    } else {
+      const int ln = q >> 3;
+      r = ln & 31;
+      c = blk * kCols + 8 * (ln >> 5) + (q & 7);
+    }
+    // forward packing: W[r0 + r][c0 + c]; transposed: W^T[c0 + r][r0 + c] = W[r0 + c][c0 + r]
+    const float f = t_new[r][c], b = t_new[c][r];
+    if constexpr (MODE == kFP32) {
+      static_cast<float*>(pj.fwd[y])[packed_index_fp32(r0 + r, c0 + c, W)] = f;
+      static_cast<float*>(pj.bwd[y])[packed_index_fp32(c0 + r, r0 + c, W)] = b;
+    } else {
+      static_cast<uint16_t*>(pj.fwd[y])[packed_index_bf16(r0 + r, c0 + c, W)] = __builtin_bit_cast(uint16_t, (__bf16)f);
+      static_cast<uint16_t*>(pj.bwd[y])[packed_index_bf16(c0 + r, r0 + c, W)] = __builtin_bit_cast(uint16_t, (__bf16)b);
+    }
+  }
+}
+
+template <int MODE>
 __global__ __launch_bounds__(256) void adam_pack_kernel(PackJob pj, float* __restrict__ p, const float* __restrict__ g,
                                                         float* __restrict__ m, float* __restrict__ v, int64_t b5_off,
                                                         AdamConsts a) {
   const int W = pj.width;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int y = blockIdx.y;
-  if (y < 3) {
-    if (idx >= (int64_t)W * W) return;
-    const int lane = pj.mode == kFP32 ? (int)((idx >> 2) & 63) : (int)((idx >> 3) & 63);
-    int row, col;
-    {
-      const int MT = W / (32 * kWaves);
-      if (pj.mode == kFP32) {
-        const int q = (int)(idx & 3);
-        int64_t chunk = idx >> 8;
-        const int i = (int)(chunk % MT);
-        chunk /= MT;
-        const int j = (int)(chunk % (W / 8)), wave = (int)(chunk / (W / 8));
-        row = 32 * (wave * MT + i) + (lane & 31);
-        col = 8 * j + 2 * q + (lane >> 5);
-      } else {
-        const int e = (int)(idx & 7);
-        int64_t chunk = idx >> 9;
-        const int i = (int)(chunk % MT);
-        chunk /= MT;
-        const int kb = (int)(chunk % (W / 16)), wave = (int)(chunk / (W / 16));
-        row = 32 * (wave * MT + i) + (lane & 31);
-        col = 16 * kb + 8 * (lane >> 5) + e;
-      }
-    }
-    const float pn = adam_update(p, g, m, v, (pj.Wl[y] - p) + (int64_t)row * W + col, a);
-    if (pj.mode == kFP32) {
-      static_cast<float*>(pj.fwd[y])[idx] = pn;
-      static_cast<float*>(pj.bwd[y])[packed_index_fp32(col, row, W)] = pn;
-    } else {
-      const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pn);
-      static_cast<uint16_t*>(pj.fwd[y])[idx] = b;
-      static_cast<uint16_t*>(pj.bwd[y])[packed_index_bf16(col, row, W)] = b;
-    }
-  } else if (y == 3) {
+  const int T = (W / 32) * (W / 32), nrv = (4 * W + 255) / 256;
+  const int b = blockIdx.x;
+  if (b < 3 * T) {
+    adam_pack_tile<MODE>(pj, p, g, m, v, a, b / T, b % T);
+  } else if (b < 3 * T + nrv) {
+    const int64_t idx = (int64_t)(b - 3 * T) * 256 + threadIdx.x;
     if (idx >= 4 * (int64_t)W) return;
     const int vi = (int)(idx / W), r = (int)(idx % W);
     const float* src = vi < 3 ? pj.bl[vi] : pj.w5;
     float* dst = vi < 3 ? pj.bh + (size_t)vi * W : pj.w5p;
     dst[lane_major_pos(r, W)] = adam_update(p, g, m, v, (src - p) + r, a);
   } else {
+    const int64_t idx = (int64_t)(b - 3 * T - nrv) * 256 + threadIdx.x;
     if (idx >= W) return;
     const int r = (int)idx;
     const int64_t w0 = (pj.W1 - p) + (int64_t)r * kInDim;
@@ -609,9 +625,13 @@ __global__ __launch_bounds__(256) void adam_pack_kernel(PackJob pj, float* __res
 
 hipError_t launch_adam_pack(const PackJob& pj, float* params, const float* grad, float* m, float* v,
                             const AdamConsts& a, int64_t b5_off, hipStream_t s) {
-  if (pj.in_dim != kInDim || (pj.mode != kFP32 && pj.mode != kBF16)) return hipErrorInvalidValue;
-  const unsigned bx = (unsigned)(((int64_t)pj.width * pj.width + 255) / 256);
-  hipLaunchKernelGGL(adam_pack_kernel, dim3(bx, 5), dim3(256), 0, s, pj, params, grad, m, v, b5_off, a);
+  if (pj.in_dim != kInDim || (pj.mode != kFP32 && pj.mode != kBF16) || pj.width % 32) return hipErrorInvalidValue;
+  const int W = pj.width;
+  const unsigned grid = (unsigned)(3 * (W / 32) * (W / 32) + (4 * W + 255) / 256 + (W + 255) / 256);
+  if (pj.mode == kFP32)
+    hipLaunchKernelGGL(adam_pack_kernel<kFP32>, dim3(grid), dim3(256), 0, s, pj, params, grad, m, v, b5_off, a);
+  else
+    hipLaunchKernelGGL(adam_pack_kernel<kBF16>, dim3(grid), dim3(256), 0, s, pj, params, grad, m, v, b5_off, a);
   return hipGetLastError();
 }
 
@@ -836,30 +856,50 @@ __device__ __forceinline__ void part_sum_entry(const PartSum& ps, int j, int lan
   if (!ps.out.base[r] || f >= ps.out.n[r]) return;
   const float* p = ps.part + (int64_t)j * ps.nparts;
   float s = 0.f;
-  for (int w = lane; w < ps.nparts; w += 64) s += p[w];
+  int w = lane;
+  for (; w + 192 < ps.nparts; w += 256) {  // four loads in flight, added in order
+    const float a0 = p[w], a1 = p[w + 64], a2 = p[w + 128], a3 = p[w + 192];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; w < ps.nparts; w += 64) s += p[w];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) ps.out.base[r][(int64_t)f * ps.out.stride[r]] = s;
 }
 
 // out_j[e] = sum over chunks (in index order) of partial[j][chunk][e], 4 elements per
-// thread; blockIdx.y == jobs.n: the training kernel's per-workgroup sums (PartSum),
-// one wave per entry.
+// thread, blocks [j bx, (j + 1) bx) for GEMM j; the blocks after those: the training
+// kernel's per-workgroup sums (PartSum), one wave per entry.
 __global__ void sum_chunks_kernel(const float* __restrict__ partial, int nchunks, int64_t n, WgradJobs jobs, int accum,
-                                  PartSum ps) {
-  const int job = blockIdx.y;
-  if (job == jobs.n) {
-    part_sum_entry(ps, blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6), threadIdx.x & 63);
+                                  PartSum ps, int bx) {
+  const int b = blockIdx.x;
+  if (b >= jobs.n * bx) {
+    part_sum_entry(ps, (b - jobs.n * bx) * (blockDim.x / 64) + (threadIdx.x >> 6), threadIdx.x & 63);
     return;
   }
-  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int job = b / bx;
+  const int64_t t = ((int64_t)(b % bx) * blockDim.x + threadIdx.x) * 4;
   if (t >= n) return;
   const float* p = partial + (int64_t)job * nchunks * n + t;
   f32x4 s = {0.f, 0.f, 0.f, 0.f};
-  for (int c = 0; c < nchunks; ++c) {
+  constexpr int U = 8;  // loads in flight; the sums still run over the chunks in order
+  int c = 0;
+  for (; c + U <= nchunks; c += U) {
+    f32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const f32x4*>(p + (int64_t)(c + u) * n);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[e] += v[u][e];
+  }
+  for (; c < nchunks; ++c) {
     const f32x4 v = *reinterpret_cast<const f32x4*>(p + (int64_t)c * n);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] += v[u];
+    for (int e = 0; e < 4; ++e) s[e] += v[e];
   }
   float* o = jobs.out[job] + t;
 #pragma unroll
@@ -887,8 +927,8 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
   const int64_t n = (int64_t)width * width;
   const unsigned bx = (unsigned)((n / 4 + 255) / 256);
   const unsigned bps = ps ? (unsigned)((kTrainSumRows * ps->width + 3) / 4) : 0u;  // 4 entries per block
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(bx > bps ? bx : bps, (unsigned)jobs.n + (ps ? 1u : 0u)), dim3(256), 0, s,
-                     partial, nchunks, n, jobs, accumulate ? 1 : 0, ps ? *ps : PartSum{});
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)jobs.n * bx + bps), dim3(256), 0, s, partial, nchunks, n, jobs,
+                     accumulate ? 1 : 0, ps ? *ps : PartSum{}, (int)bx);
   return hipGetLastError();
 }
 

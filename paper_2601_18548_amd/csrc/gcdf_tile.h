@@ -668,6 +668,7 @@ struct TileDump {
   // row 15 (first entry) the fused loss sum_i (d_i - target_i)^2 / B
   float* bsum;
   __bf16* vt;  // with bsum: the tile's network inputs, transposed, BF16 hi [9][64] then lo
+  float* sp1;  // BF16: SiLU'(z1) of the input layer kept in LDS for the reverse sweep (see keep_sp1)
   int width;
   __device__ __forceinline__ float* row(int r) const { return bsum ? bsum + r * width : nullptr; }
   __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
@@ -746,7 +747,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
           float v[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            v[q] = silu_only(acc[I][NT][8 * GP + q]);
+            // SiLU' replaces z4 in the accumulator, for g4 below
+            float dv;
+            silu_fwd(acc[I][NT][8 * GP + q], v[q], dv);
+            acc[I][NT][8 * GP + q] = dv;
             dpart[NT] += w5r[q >> 2][q & 3] * v[q];
           }
           act_store_pair<W, MODE, I, GP, NT>(ln, v);
@@ -818,7 +822,8 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         for (int q = 0; q < 8; ++q) {
           const int j = 8 * GP + q;  // accumulator element: g = 2 GP + q/4, r = q%4
           float hv, dv;
-          silu_fwd(acc[I][NT][j], hv, dv);
+          if constexpr (TRAIN && L == 2) dv = acc[I][NT][j];  // SiLU'(z4), kept above
+          else silu_fwd(acc[I][NT][j], hv, dv);
           if constexpr (L < 2) {
             sp[L][I][NT][j] = park(dv);
             v[q] = hv;
@@ -916,8 +921,22 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
   if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
   layer_gemm<W, MODE, rev_arith<MODE>(), rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
   float g1keep[TRAIN ? MT : 1][2][16];
+  constexpr bool KEPT = TRAIN && MODE == kBF16;  // SiLU'(z1) kept by the input layer
+  if constexpr (KEPT) {
+    constexpr int T = Geo<W, MODE>::THREADS;
 #pragma unroll
-  for (int i = 0; i < MT; ++i)
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 sv = *reinterpret_cast<const f32x4*>(td.sp1 + (((i * 2 + nt) * 4 + g) * T + threadIdx.x) * 4);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) g1keep[i][nt][4 * g + r] = acc[i][nt][4 * g + r] * sv[r];
+        }
+  }
+#pragma unroll
+  for (int i = 0; i < (KEPT ? 0 : MT); ++i)
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -976,9 +995,10 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
   }
 }
 
-// Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.
-template <int W, int MODE, bool PAIRS, bool SPH>
-__device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b) {
+// Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.  KEEP: SiLU'(z1)
+// also goes to sp1 (train_sp1's layout) for the reverse sweep.
+template <int W, int MODE, bool PAIRS, bool SPH, bool KEEP = false>
+__device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b, float* sp1 = nullptr) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   static_for<MT>([&](auto I) {
@@ -1000,14 +1020,24 @@ __device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W
       }
       static_for<2>([&](auto NT) {
         const float* x = b.xin + NT * 32 * XF;
-        float v[8];
+        float v[8], dv[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           float c = PAIRS ? 0.f : cr[q];
           if constexpr (PAIRS) c = arm_term(wa[q][3], wb[q][0], wb[q][1], wb[q][2], wb[q][3], wc[q][0], wc[q][1], x + 5);
-          v[q] = silu_only(input_preact_t<SPH>(c, wa[q][0], wa[q][1], wa[q][2], wr[q], x));
+          const float z = input_preact_t<SPH>(c, wa[q][0], wa[q][1], wa[q][2], wr[q], x);
+          if constexpr (KEEP) silu_fwd(z, v[q], dv[q]);
+          else v[q] = silu_only(z);
         }
         act_store_pair<W, MODE, I, GP, NT>(ln, v);
+        if constexpr (KEEP) {
+          constexpr int T = Geo<W, MODE>::THREADS;
+          constexpr int k = ((I * 2 + NT) * 16 + 8 * GP) / 4;  // first of the two 16-byte groups
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<f32x4*>(sp1 + ((k + h) * T + threadIdx.x) * 4) =
+                f32x4{dv[4 * h], dv[4 * h + 1], dv[4 * h + 2], dv[4 * h + 3]};
+        }
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -1068,7 +1098,8 @@ struct TileCtx {
 // (TileDump::vt).
 template <int W, int MODE>
 constexpr int train_extra_lds() {
-  return Geo<W, MODE>::NW * kTileQ * 4 + (MODE == kBF16 ? kTrainSumRows * W * 4 + 2 * 9 * kTileQ * 2 : 0);
+  return Geo<W, MODE>::NW * kTileQ * 4 +
+         (MODE == kBF16 ? kTrainSumRows * W * 4 + 2 * 9 * kTileQ * 2 + W * kTileQ * 4 : 0);
 }
 template <int W, int MODE>
 __device__ __forceinline__ float* train_bsum(char* lds) {
@@ -1078,6 +1109,14 @@ __device__ __forceinline__ float* train_bsum(char* lds) {
 template <int W, int MODE>
 __device__ __forceinline__ __bf16* train_vt(char* lds) {
   if constexpr (MODE == kBF16) return reinterpret_cast<__bf16*>(train_bsum<W, MODE>(lds) + kTrainSumRows * W);
+  return nullptr;
+}
+// BF16 training: SiLU'(z1) of the tile (W x 64 floats), written by the input layer
+// and read back by the last reverse layer, each thread its own values (16-byte
+// group k of thread t at float (k THREADS + t) 4), so no barrier orders them.
+template <int W, int MODE>
+__device__ __forceinline__ float* train_sp1(char* lds) {
+  if constexpr (MODE == kBF16) return reinterpret_cast<float*>(train_vt<W, MODE>(lds) + 2 * 9 * kTileQ);
   return nullptr;
 }
 
@@ -1194,6 +1233,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.dred = reinterpret_cast<float*>(tc.act + G::LDS_BYTES);
     td.bsum = train_bsum<W, MODE>(tc.act);
     td.vt = train_vt<W, MODE>(tc.act);
+    td.sp1 = train_sp1<W, MODE>(tc.act);
     td.width = W;
     td.xin = xin;
     td.target = job.seed ? nullptr : job.target;
@@ -1203,7 +1243,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.mse_scale = job.mse_scale;
     td.inv_b = job.inv_b;
   }
-  fwd_input<W, MODE, PAIRS, SPH>(ln, b);
+  fwd_input<W, MODE, PAIRS, SPH, TRAIN && MODE == kBF16>(ln, b, td.sp1);
   __syncthreads();
   if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.stage, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
 
@@ -1337,6 +1377,8 @@ __device__ __forceinline__ void report_overflow(const DevNet& net, const TileCtx
 template <int W, int MODE, bool PAIRS, int OCC, bool TRAIN = false, bool GATHER = false, bool SPH = false>
 __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(const DevNet net, const Job job, int want_grad,
                                                              int64_t ntiles) {
+  static_assert(Geo<W, MODE>::LDS_BYTES + (TRAIN ? train_extra_lds<W, MODE>() : 0) + 16 <= 160 * 1024,
+                "the workgroup's LDS exceeds the compute unit's 160 KiB");
   __shared__ __attribute__((aligned(16))) char lds[Geo<W, MODE>::LDS_BYTES + (TRAIN ? train_extra_lds<W, MODE>() : 0)];
   __shared__ uint32_t ovf;
   TileCtx<W, MODE> tc(lds, &ovf, net, threadIdx.x);
