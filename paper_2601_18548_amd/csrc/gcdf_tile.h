@@ -110,6 +110,7 @@ __device__ __forceinline__ float input_preact(float c, float w0, float w1, float
 // z1 = c + W1[r][0] p'x + W1[r][1] p'y + W1[r][2] p'z + W1[r][radius] r, with r
 // at position kXinRadius of the per-query record.
 constexpr int kXinRadius = 12;
+constexpr int kXinTarget = 13;  // training with the fused loss: the sample's target distance
 template <bool SPH>
 __device__ __forceinline__ float input_preact_t(float c, float w0, float w1, float w2, float wr, const float* x) {
   if constexpr (SPH) return input_preact(c, w0, w1, w2, x) + wr * x[kXinRadius];
@@ -172,7 +173,7 @@ struct Geo {
   static constexpr int LO_OFF = 2048;
   static constexpr int NK8 = W / 8;                  // 8-deep K groups (fp32: 4 MFMAs of K=2)
   static constexpr int ACT_BYTES = W * kTileQ * 4;   // fp32, or bf16 hi + bf16 lo
-  static constexpr int XIN_FLOATS = 17;              // per query: p'(3), cos, sin, arm(6), seed, radius, pad; odd stride: lanes reading one field of 32 queries hit 32 different banks
+  static constexpr int XIN_FLOATS = 17;              // per query: p'(3), cos, sin, arm(6), seed, radius, target, pad; odd stride: lanes reading one field of 32 queries hit 32 different banks
   static constexpr int RED_VALS = 10;                // d + 9 input-gradient components
   static constexpr int RED_BYTES = NW * RED_VALS * kTileQ * 4;
   static constexpr int LDS_BYTES = ACT_BYTES + kTileQ * XIN_FLOATS * 4 + W * 4 + (RED_IN_ACT ? 0 : RED_BYTES) + 4 * W * 4;
@@ -637,6 +638,7 @@ struct Bases {
   const float* bh;    // LDS copy of b2, b3, b4 (lane-major), at this lane's block
   const float* w5;    // LDS copy of w_out (lane-major), at this lane's block
   const float* w1;    // input layer rows (lane-major, 12 floats per row), at this lane's block
+  const float* w1a;   // input layer row rbase + lane%32 (its A fragment row in M tile 0; tile i at +16 i rows)
   const float* crow;  // per-knot input-layer constant (LDS, lane-major), at this lane's block
   const float* xin;   // xin + n0 * XIN_FLOATS
   int voff;           // lane offset inside a matrix's fragment stream (see load_a)
@@ -661,6 +663,7 @@ struct TileDump {
   float* sq_out;
   float* d_out;  // the distances, when asked for
   float mse_scale, inv_b;
+  float b5;  // the output bias
   // per-workgroup sums over its samples (LDS, [kTrainSumRows][width]; NULL when
   // these gradients are reduced from the dumps instead): rows 0..3 the bias
   // gradients sum_i g_l (l = 1..4), row 4 dL/dw_out = sum_i seed_i h4_i, rows
@@ -774,10 +777,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
         float sum = td.dred[n];
 #pragma unroll
         for (int w = 1; w < Geo<W, MODE>::NW; ++w) sum += td.dred[w * kTileQ + n];
-        const float dv = sum + *net.b5p;
+        const float dv = sum + td.b5;
         const bool valid = n < td.nvalid;
         const int64_t q = td.q0 + n;
-        const float r = valid ? dv - td.target[q] : 0.f;
+        const float r = valid ? dv - td.xin[n * Geo<W, MODE>::XIN_FLOATS + kXinTarget] : 0.f;
         const float seed = td.mse_scale * r;  // dL/dd for L = mean (d - target)^2
         sq = td.inv_b * (r * r);
         *seedp = seed;
@@ -910,11 +913,67 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   }
 }
 
+// Pure-BF16 pair-list tiles of width 256 (point obstacles; the training
+// configuration) take the input layer's
+// pre-activations from the matrix cores: z1 = b1 + W1 v over the 9 inputs, K
+// padded to 16 (p' at k = 0..2, the arm joints at 3..8), as the split products
+// W1h vh + W1h vl + W1l vh accumulated in FP32 (h: the BF16 rounding, l: the BF16
+// rounding of the rest; the terms left out are below 2^-16 |W1| |v|).  The
+// prologue stages the tile's inputs as B fragments at `vb` (query n at byte 64 n:
+// 16 BF16 hi, then 16 lo).  The forward and the reverse sweep's recomputation
+// both call this for M tile I, so they see the same z1.
+template <int W, int MODE>
+constexpr bool mma_input(bool pairs, bool sph) {
+  return W == 256 && MODE == kBF16 && pairs && !sph;  // (at width 512 the recomputation would spill)
+}
+constexpr int kVbBytes = 64;  // per query: B fragments of the inputs, hi then lo
+
+template <int W, int MODE, int I>
+__device__ __forceinline__ void input_gemm(const Lane<W, MODE>& ln, const Bases<W, MODE>& b, const char* vb,
+                                           f32x16 (&z)[2]) {
+  bf16x8 bh[2], bl[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const char* p = vb + (32 * nt + ln.n0) * kVbBytes + ln.kh * 16;
+    bh[nt] = *reinterpret_cast<const bf16x8*>(p);
+    bl[nt] = *reinterpret_cast<const bf16x8*>(p + 32);
+  }
+  // A: row m = lane%32 of the tile, inputs 8 kh .. 8 kh + 7
+  const float* w = b.w1a + I * 16 * 12;
+  const f32x4 wa = *reinterpret_cast<const f32x4*>(w);
+  const f32x4 wb = *reinterpret_cast<const f32x4*>(w + 4);
+  const f32x2 wc = *reinterpret_cast<const f32x2*>(w + 8);
+  const float lo8[8] = {wa[0], wa[1], wa[2], wb[0], wb[1], wb[2], wb[3], wc[0]};  // k = 0..7 (slot 3 is b1)
+  bf16x8 ah, al;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float a = ln.kh ? (e == 0 ? wc[1] : 0.f) : lo8[e];  // k = 8: the last arm joint
+    const __bf16 hi = (__bf16)a;
+    ah[e] = hi;
+    al[e] = (__bf16)(a - (float)hi);
+  }
+  // b1 of the accumulator layout's rows (lane-major block of this lane)
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float bias = b.w1[(16 * I + 4 * g + r) * 12 + 3];
+      z[0][4 * g + r] = bias;
+      z[1][4 * g + r] = bias;
+    }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nt], z[nt], 0, 0, 0);
+    z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nt], z[nt], 0, 0, 0);
+    z[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nt], z[nt], 0, 0, 0);
+  }
+}
+
 // Last reverse layer: g1 = (W2^T g2) * SiLU'(z1) with z1 recomputed, then the
 // input-layer gradient e = W1^T g1 accumulated per lane in FP32.
 template <int W, int MODE, bool PAIRS, bool TRAIN, bool SPH>
 __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                          float (&epart)[2][9], const TileDump& td) {
+                                          float (&epart)[2][9], const TileDump& td, const char* vb) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   f32x16 acc[MT][2];
@@ -935,8 +994,42 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
           for (int r = 0; r < 4; ++r) g1keep[i][nt][4 * g + r] = acc[i][nt][4 * g + r] * sv[r];
         }
   }
+  constexpr bool MMA = !KEPT && mma_input<W, MODE>(PAIRS, SPH);  // z1 from the matrix cores again
+  if constexpr (MMA) {
+    static_for<MT>([&](auto I) {
+      f32x16 z[2];
+      input_gemm<W, MODE, I>(ln, b, vb, z);
 #pragma unroll
-  for (int i = 0; i < (KEPT ? 0 : MT); ++i)
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float* w = b.w1 + (16 * I + 4 * g + r) * 12;
+          const f32x4 wa = *reinterpret_cast<const f32x4*>(w);
+          const f32x4 wb = *reinterpret_cast<const f32x4*>(w + 4);
+          const f32x2 wc = *reinterpret_cast<const f32x2*>(w + 8);
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            const float g1 = acc[I][nt][4 * g + r] * silu_prime_only(z[nt][4 * g + r]);
+            if constexpr (TRAIN) {
+              g1keep[I][nt][4 * g + r] = g1;
+            } else {
+              epart[nt][0] += wa[0] * g1;
+              epart[nt][1] += wa[1] * g1;
+              epart[nt][2] += wa[2] * g1;
+              epart[nt][3] += wb[0] * g1;
+              epart[nt][4] += wb[1] * g1;
+              epart[nt][5] += wb[2] * g1;
+              epart[nt][6] += wb[3] * g1;
+              epart[nt][7] += wc[0] * g1;
+              epart[nt][8] += wc[1] * g1;
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+    });
+  }
+#pragma unroll
+  for (int i = 0; i < ((KEPT || MMA) ? 0 : MT); ++i)
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -998,9 +1091,37 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
 // Input layer (FP32): z1 = W1 [p'; a] + b1, h1 = SiLU(z1) -> LDS.  KEEP: SiLU'(z1)
 // also goes to sp1 (train_sp1's layout) for the reverse sweep.
 template <int W, int MODE, bool PAIRS, bool SPH, bool KEEP = false>
-__device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b, float* sp1 = nullptr) {
+__device__ __forceinline__ void fwd_input(const Lane<W, MODE>& ln, const Bases<W, MODE>& b, const char* vb,
+                                          float* sp1 = nullptr) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
+  if constexpr (mma_input<W, MODE>(PAIRS, SPH)) {
+    static_for<MT>([&](auto I) {
+      f32x16 z[2];
+      input_gemm<W, MODE, I>(ln, b, vb, z);
+      static_for<2>([&](auto GP) {
+        static_for<2>([&](auto NT) {
+          float v[8], dv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if constexpr (KEEP) silu_fwd(z[NT][8 * GP + q], v[q], dv[q]);
+            else v[q] = silu_only(z[NT][8 * GP + q]);
+          }
+          act_store_pair<W, MODE, I, GP, NT>(ln, v);
+          if constexpr (KEEP) {
+            constexpr int T = Geo<W, MODE>::THREADS;
+            constexpr int k = ((I * 2 + NT) * 16 + 8 * GP) / 4;  // first of the two 16-byte groups
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              *reinterpret_cast<f32x4*>(sp1 + ((k + h) * T + threadIdx.x) * 4) =
+                  f32x4{dv[4 * h], dv[4 * h + 1], dv[4 * h + 2], dv[4 * h + 3]};
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    });
+    return;
+  }
   static_for<MT>([&](auto I) {
     static_for<2>([&](auto GP) {
       f32x4 wa[8], wb[8];
@@ -1054,10 +1175,11 @@ struct TileCtx {
   float* crow;  // [W]
   float* red;   // [waves][10][64]
   uint32_t* ovf;  // LDS word: a tile of this workgroup overflowed FP16 (see report_overflow)
+  float b5;       // the output bias, read once (every tile's final sum adds it)
   Lane<W, MODE> ln;
   Bases<W, MODE> b;
   __device__ __forceinline__ TileCtx(char* lds, uint32_t* ovf_word, const DevNet& net, int tid)
-      : act(lds), ovf(ovf_word), ln(lds, tid) {
+      : act(lds), ovf(ovf_word), b5(*net.b5p), ln(lds, tid) {
     if (tid == 0) *ovf = 0u;  // ordered before any tile's use by the tile's first barrier
     using G = Geo<W, MODE>;
     constexpr int MT = G::MT;
@@ -1080,6 +1202,10 @@ struct TileCtx {
     b.bh = vec + lblk;
     b.w5 = vec + 3 * W + lblk;
     b.w1 = net.w1p + lblk * 12;
+    {  // row m = lane%32 of M tile 0 is lane-major row ((pw 2 + h_m) PMT + sub MT) 16 + 4 g_m + r_m
+      const int m = ln.n0;
+      b.w1a = net.w1p + ((((pw * 2 + ((m >> 2) & 1)) * G::PMT + sub * MT) * 16) + 4 * (m >> 3) + (m & 3)) * 12;
+    }
     b.crow = crow + lblk;
     b.xin = xin + ln.n0 * G::XIN_FLOATS;
     b.voff = (int)(pw * stream_bytes) + sub * MT * 1024 + ln.lane * 16;
@@ -1185,6 +1311,8 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
     // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact)
     x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : 1.f;
+    // the fused loss's target, fetched with the inputs rather than after the forward
+    if constexpr (TRAIN) x[kXinTarget] = (!job.seed && job.target && q < qlimit) ? job.target[qc] : 0.f;
     if constexpr (TRAIN && MODE == kBF16) {
       // the network inputs transposed and split into BF16 hi + lo, for dW1 on the
       // matrix cores (the ragged tail's inputs meet zero gradients)
@@ -1198,6 +1326,23 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       }
     }
     if constexpr (SPH) x[kXinRadius] = pxyz[3];  // the radius passes through the rigid transform
+    if constexpr (mma_input<W, MODE>(PAIRS, SPH)) {
+      // the inputs as B fragments of the matrix-core input layer (input_gemm), in
+      // the idle half of the activation tile
+      const float v[16] = {x[0], x[1], x[2], x[5], x[6], x[7], x[8], x[9], x[10], 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bf16x8 vh[2], vl[2];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const __bf16 hi = (__bf16)v[k];
+        vh[k >> 3][k & 7] = hi;
+        vl[k >> 3][k & 7] = (__bf16)(v[k] - (float)hi);
+      }
+      char* o = tc.act + G::ACT_BYTES / 2 + tid * kVbBytes;
+      *reinterpret_cast<bf16x8*>(o) = vh[0];
+      *reinterpret_cast<bf16x8*>(o + 16) = vh[1];
+      *reinterpret_cast<bf16x8*>(o + 32) = vl[0];
+      *reinterpret_cast<bf16x8*>(o + 48) = vl[1];
+    }
     if constexpr (PAIRS) {
       if (job.dumpV) {
         const bool ok = q < qlimit;
@@ -1241,9 +1386,10 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     td.sq_out = job.sq_out;
     td.d_out = job.seed ? nullptr : job.d;
     td.mse_scale = job.mse_scale;
+    td.b5 = tc.b5;
     td.inv_b = job.inv_b;
   }
-  fwd_input<W, MODE, PAIRS, SPH, TRAIN && MODE == kBF16>(ln, b, td.sp1);
+  fwd_input<W, MODE, PAIRS, SPH, TRAIN && MODE == kBF16>(ln, b, tc.act + G::ACT_BYTES / 2, td.sp1);
   __syncthreads();
   if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.stage, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
 
@@ -1263,7 +1409,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   if (want_grad) {
     bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td);
     bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td);
-    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td);
+    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td, tc.act + G::ACT_BYTES / 2);
     if constexpr (rev_arith<MODE>() == kF16) {
       // a lane whose output partial sum is finite but whose input-gradient partial
       // sums are not: the FP16 reverse sweep overflowed (the forward accumulates in
@@ -1323,7 +1469,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 #pragma unroll
         for (int c = 1; c < G::RED_VALS; ++c) vals[c] *= 1.0f / rev_scale<MODE>();
       }
-      const float dv = vals[0] + *net.b5p;
+      const float dv = vals[0] + tc.b5;
       const int64_t q = q0 + n;
       const bool valid = q < qlimit;
       const int64_t out = (PAIRS || GATHER) ? q : kk * job.Np + q;
