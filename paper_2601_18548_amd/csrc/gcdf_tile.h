@@ -427,17 +427,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* base) 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
-// ZERO: acc starts at zero (its contents on entry are not read).
+// The A fragments of a layer's first two K steps, loaded ahead of the layer.
+// Training loads them before the previous layer's dump: the vector-memory counter
+// completes in order, so a wait for fragments issued after the dump's stores
+// would also wait for those stores.
+template <int W, int MODE>
+struct APre {
+  f32x4 a0[Geo<W, MODE>::MT], a1[Geo<W, MODE>::MT];
+};
+template <int W, int MODE>
+__device__ __forceinline__ void preload_a(APre<W, MODE>& p, __amdgpu_buffer_rsrc_t rs, int voff) {
+  load_a<W, MODE>(p.a0, rs, voff, 0);
+  load_a<W, MODE>(p.a1, rs, voff, 1);
+}
+
+// ZERO: acc starts at zero (its contents on entry are not read).  a0, a1: the A
+// fragments of steps 0 and 1, already requested (preload_a).
 template <int W, int MODE, int AM, bool ZERO = false>
-__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs, int voff,
-                                           const char* br) {
-  constexpr int MT = Geo<W, MODE>::MT;
+__device__ __forceinline__ void layer_gemm_pre(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs,
+                                               int voff, const char* br, f32x4 (&a0)[(Geo<W, MODE>::MT)],
+                                               f32x4 (&a1)[(Geo<W, MODE>::MT)]) {
   constexpr int NS = (MODE == kFP32) ? Geo<W, MODE>::NK8 : Geo<W, MODE>::NKB;  // even, >= 16
   constexpr int SB = Geo<W, MODE>::STEP_BYTES;
-  f32x4 a0[MT], a1[MT];
   BFrag<AM> b0, b1;
-  load_a<W, MODE>(a0, rs, voff, 0);
-  load_a<W, MODE>(a1, rs, voff, 1);
   load_b<W, MODE, AM>(b0, br);
   int s = 0;
   if constexpr (ZERO) {  // steps 0 and 1, the first writing acc from a zero C operand
@@ -460,6 +472,14 @@ __device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2],
     mma_step_reload<W, MODE, AM>(acc, a1, b1, rs, voff, s + 3 < NS ? s + 3 : NS - 1);
     br += 2 * SB;
   }
+}
+
+template <int W, int MODE, int AM, bool ZERO = false>
+__device__ __forceinline__ void layer_gemm(f32x16 (&acc)[(Geo<W, MODE>::MT)][2], __amdgpu_buffer_rsrc_t rs, int voff,
+                                           const char* br) {
+  APre<W, MODE> p;
+  preload_a<W, MODE>(p, rs, voff);
+  layer_gemm_pre<W, MODE, AM, ZERO>(acc, rs, voff, br, p.a0, p.a1);
 }
 
 // The reverse layers' accumulators start at zero: in single FP16 the first
@@ -716,7 +736,7 @@ __device__ __forceinline__ void write_packed(const Lane<W, MODE>& ln, const f32x
 template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
                                            float (&sp)[2][(Geo<W, MODE>::MT)][2][16], float (&dpart)[2], int want_grad,
-                                           const TileDump& td) {
+                                           const TileDump& td, APre<W, MODE>& ap) {
   constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
 #pragma unroll
@@ -729,7 +749,10 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][nt][4 * g + r] = b4[r];
     }
-  layer_gemm<W, MODE, fwd_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
+  if constexpr (TRAIN)
+    layer_gemm_pre<W, MODE, fwd_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r, ap.a0, ap.a1);
+  else
+    layer_gemm<W, MODE, fwd_arith<MODE>()>(acc, stream_rsrc<W, MODE>(net.fwd[L]), b.voff, ln.act_r);
   // arithmetic of what this layer stores: the next layer's activations, or g4
   // for the reverse sweep
   constexpr int SA = L == 2 ? rev_arith<MODE>() : fwd_arith<MODE>();
@@ -857,6 +880,7 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
   // training: h2, h3 (layers 2, 3) or g4 (layer 4) to HBM; the tile is next
   // overwritten only after the following K loop and its barrier
   if constexpr (TRAIN) {  // h2, h3, or g4 (with db4 = sum_i g4_i)
+    preload_a<W, MODE>(ap, stream_rsrc<W, MODE>(L < 2 ? net.fwd[L + 1] : net.bwd[2]), b.voff);  // the next layer's
     const DumpSums sm{td.row(3), nullptr, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, L < 2 ? td.h(L + 1) : td.g(3), td.ldb, td.q0, td.nvalid,
                        (L == 2 && td.bsum) ? &sm : nullptr);
@@ -865,7 +889,8 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
 
 template <int W, int MODE, int L, bool TRAIN>
 __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                           const float (&sp)[2][(Geo<W, MODE>::MT)][2][16], const TileDump& td) {
+                                           const float (&sp)[2][(Geo<W, MODE>::MT)][2][16], const TileDump& td,
+                                           APre<W, MODE>& ap) {
   constexpr int MT = Geo<W, MODE>::MT;
   f32x16 acc[MT][2];
   constexpr int RA = rev_arith<MODE>();
@@ -875,7 +900,10 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   constexpr bool PP = RA == kF16 && !TRAIN;
   const char* br = (PP && L == 1) ? ln.act_r + Geo<W, MODE>::LO_OFF : ln.act_r;
   if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
-  layer_gemm<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, br);
+  if constexpr (TRAIN)
+    layer_gemm_pre<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, br, ap.a0, ap.a1);
+  else
+    layer_gemm<W, MODE, RA, rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[L]), b.voff, br);
   constexpr bool DEFER = !PP && defer_stores<W, MODE, TRAIN>(false);  // as in fwd_hidden
   if constexpr (!DEFER && !PP) __syncthreads();
   static_for<MT>([&](auto I) {
@@ -908,6 +936,7 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
   }
   __syncthreads();
   if constexpr (TRAIN) {  // g3 or g2, with their bias sums
+    preload_a<W, MODE>(ap, stream_rsrc<W, MODE>(net.bwd[L - 1]), b.voff);  // the next layer's
     const DumpSums sm{td.row(L), nullptr, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.g(L), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr);
   }
@@ -973,12 +1002,18 @@ __device__ __forceinline__ void input_gemm(const Lane<W, MODE>& ln, const Bases<
 // input-layer gradient e = W1^T g1 accumulated per lane in FP32.
 template <int W, int MODE, bool PAIRS, bool TRAIN, bool SPH>
 __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
-                                          float (&epart)[2][9], const TileDump& td, const char* vb) {
+                                          float (&epart)[2][9], const TileDump& td, const char* vb,
+                                          APre<W, MODE>& ap) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   f32x16 acc[MT][2];
   if constexpr (!rev_zero_c<MODE>()) zero_acc<W, MODE>(acc);
-  layer_gemm<W, MODE, rev_arith<MODE>(), rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff, ln.act_r);
+  if constexpr (TRAIN)
+    layer_gemm_pre<W, MODE, rev_arith<MODE>(), rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff,
+                                                                   ln.act_r, ap.a0, ap.a1);
+  else
+    layer_gemm<W, MODE, rev_arith<MODE>(), rev_zero_c<MODE>()>(acc, stream_rsrc<W, MODE>(net.bwd[0]), b.voff,
+                                                               ln.act_r);
   float g1keep[TRAIN ? MT : 1][2][16];
   constexpr bool KEPT = TRAIN && MODE == kBF16;  // SiLU'(z1) kept by the input layer
   if constexpr (KEPT) {
@@ -1391,14 +1426,18 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   }
   fwd_input<W, MODE, PAIRS, SPH, TRAIN && MODE == kBF16>(ln, b, tc.act + G::ACT_BYTES / 2, td.sp1);
   __syncthreads();
-  if constexpr (TRAIN) dump_tile<W, MODE>(td.act, td.stage, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
+  APre<W, MODE> ap;  // training: each layer's first weight fragments, requested before the dump ahead of it
+  if constexpr (TRAIN) {
+    preload_a<W, MODE>(ap, stream_rsrc<W, MODE>(net.fwd[0]), b.voff);
+    dump_tile<W, MODE>(td.act, td.stage, td.h(0), td.ldb, td.q0, td.nvalid);  // h1
+  }
 
   // ---- hidden layers 2..4 (forward), keeping SiLU' of layers 2 and 3 ----
   float sp[2][MT][2][16];
   float dpart[2] = {0.f, 0.f};
-  fwd_hidden<W, MODE, 0, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
-  fwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
-  fwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, dpart, want_grad, td);
+  fwd_hidden<W, MODE, 0, TRAIN>(net, ln, b, sp, dpart, want_grad, td, ap);
+  fwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, dpart, want_grad, td, ap);
+  fwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, dpart, want_grad, td, ap);
 
   // ---- reverse sweep: W4^T, W3^T (into LDS), W2^T (into the input-layer gradient) ----
   float epart[2][9];
@@ -1407,9 +1446,9 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
 #pragma unroll
     for (int c = 0; c < 9; ++c) epart[nt][c] = 0.f;
   if (want_grad) {
-    bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td);
-    bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td);
-    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td, tc.act + G::ACT_BYTES / 2);
+    bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td, ap);
+    bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td, ap);
+    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td, tc.act + G::ACT_BYTES / 2, ap);
     if constexpr (rev_arith<MODE>() == kF16) {
       // a lane whose output partial sum is finite but whose input-gradient partial
       // sums are not: the FP16 reverse sweep overflowed (the forward accumulates in
