@@ -563,8 +563,12 @@ __device__ __forceinline__ void dump_tile(const char* act, char* stage, void* ds
     const char* a = act;
     constexpr int NG = W / 8;  // feature groups
     constexpr int NP = W * (kTileQ / 8);  // pieces: (query block nb, feature f) at nb W + f
-    for (int t = threadIdx.x; t < NG * (kTileQ / 8); t += Geo<W, MODE>::THREADS) {
-      const int g8 = t % NG, nb = t / NG;
+    // Each wave stages exactly the pieces it copies out below (features 32 w ..
+    // 32 w + 31: feature groups 4 w .. 4 w + 3, every query block), so the copy
+    // needs no workgroup barrier: one wave's LDS operations complete in order.
+    static_assert(Geo<W, MODE>::NW * 4 == NG, "each wave stages four feature groups");
+    if ((threadIdx.x & 63) < 32) {
+      const int g8 = 4 * (threadIdx.x >> 6) + (threadIdx.x & 3), nb = (threadIdx.x & 31) >> 2;
       const int gbyte = (g8 >> 1) * Geo<W, MODE>::STEP_BYTES + (g8 & 1) * 1024;  // 16-feature step, 8-feature half
       u32x4 m[8];
 #pragma unroll
@@ -584,7 +588,7 @@ __device__ __forceinline__ void dump_tile(const char* act, char* stage, void* ds
         *reinterpret_cast<u32x4*>(stage + (P ^ ((P >> 4) & 7)) * 16) = row;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     // the tile's pieces are consecutive in the dump: piece P at element ((q0 / 8) W + P) 8
     constexpr int T = Geo<W, MODE>::THREADS;
     static_assert(T % W == 0, "a thread's pieces share one feature");
@@ -829,7 +833,9 @@ __device__ __forceinline__ void fwd_hidden(const DevNet& net, const Lane<W, MODE
       }
     }
     // h4 is needed only for dL/dw_out = sum_i seed_i h4_i: summed here when the
-    // tile engine keeps the bias sums, else written out
+    // tile engine keeps the bias sums, else written out (after a barrier: wave 0
+    // wrote the seeds the copy reads)
+    __syncthreads();
     const DumpSums sm{td.row(4), td.xin + 11, nullptr, td.vt};
     dump_tile<W, MODE>(td.act, td.stage, td.h(3), td.ldb, td.q0, td.nvalid, td.bsum ? &sm : nullptr, !td.bsum);
     __syncthreads();  // h4 fully read before g4 overwrites the tile; seeds written
