@@ -703,12 +703,12 @@ struct TileDump {
 };
 
 // Whether a hidden-layer epilogue keeps its packed results in registers across
-// the barrier (two waves per SIMD, not training).  At width 512 the last
-// forward layer, which also carries the output-layer sums, would spill, so it
-// stores after the barrier as before.
+// the barrier (two waves per SIMD).  At width 512 the last forward layer, which
+// also carries the output-layer sums, would spill, so it stores after the barrier
+// as before; so does training's last forward layer, which stores h4 first.
 template <int W, int MODE, bool TRAIN>
 constexpr bool defer_stores(bool last_forward) {
-  return Geo<W, MODE>::SUB > 1 && !TRAIN && (!last_forward || Geo<W, MODE>::MT == 1);
+  return Geo<W, MODE>::SUB > 1 && (!last_forward || (Geo<W, MODE>::MT == 1 && !TRAIN));
 }
 
 // The packed words of elements 8 GP .. 8 GP + 7 of an accumulator go back into
