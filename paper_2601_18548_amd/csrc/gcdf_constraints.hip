@@ -153,32 +153,40 @@ __global__ __launch_bounds__(kPartThreads) void partition_fill_kernel(const floa
 }
 
 // One workgroup: tile_off[0] = 0, tile_off[i+1] = tile_off[i] + ceil(m_i / 64) with
-// m_i = offsets[i+1] - offsets[i] (the gathered tiles of the CSR query).
-__global__ __launch_bounds__(kPartThreads) void csr_tile_offsets_kernel(const int64_t* __restrict__ offsets, int64_t N,
+// m_i = offsets[i+1] - offsets[i] (the gathered tiles of the CSR query).  Thread t
+// takes the contiguous knots [t L, (t + 1) L), L = ceil(N / 1024): it sums their
+// tile counts, the workgroup scans the 1024 sums, and the thread writes its
+// knots' offsets from its base (two passes over the offsets, two barriers per
+// scan step, however large N is).
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void csr_tile_offsets_kernel(const int64_t* __restrict__ offsets, int64_t N,
                                                                         int64_t* __restrict__ tile_off) {
-  __shared__ int64_t buf[kPartThreads];
-  __shared__ int64_t carry;
-  if (threadIdx.x == 0) {
-    carry = 0;
-    tile_off[0] = 0;
-  }
+  __shared__ int64_t buf[kScanThreads];
+  const int t = threadIdx.x;
+  const int64_t L = (N + kScanThreads - 1) / kScanThreads;
+  const int64_t i0 = t * L < N ? t * L : N;
+  const int64_t i1 = i0 + L < N ? i0 + L : N;
+  auto tiles = [&](int64_t i) {
+    const int64_t m = offsets[i + 1] - offsets[i];
+    return m > 0 ? (m + kTileQ - 1) / kTileQ : (int64_t)0;
+  };
+  int64_t sum = 0;
+#pragma unroll 8
+  for (int64_t i = i0; i < i1; ++i) sum += tiles(i);
+  buf[t] = sum;
   __syncthreads();
-  for (int64_t b = 0; b < N; b += kPartThreads) {
-    const int64_t i = b + threadIdx.x;
-    const int64_t m = i < N ? offsets[i + 1] - offsets[i] : 0;
-    buf[threadIdx.x] = m > 0 ? (m + kTileQ - 1) / kTileQ : 0;
+  for (int o = 1; o < kScanThreads; o <<= 1) {  // inclusive scan of the segment sums
+    const int64_t add = t >= o ? buf[t - o] : 0;
     __syncthreads();
-    for (int o = 1; o < kPartThreads; o <<= 1) {
-      const int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-      __syncthreads();
-      buf[threadIdx.x] += add;
-      __syncthreads();
-    }
-    const int64_t base = carry;
-    if (i < N) tile_off[i + 1] = base + buf[threadIdx.x];
+    buf[t] += add;
     __syncthreads();
-    if (threadIdx.x == kPartThreads - 1) carry = base + buf[kPartThreads - 1];
-    __syncthreads();
+  }
+  int64_t run = buf[t] - sum;  // tiles of the knots before this segment
+  if (t == 0) tile_off[0] = 0;
+#pragma unroll 8
+  for (int64_t i = i0; i < i1; ++i) {
+    run += tiles(i);
+    tile_off[i + 1] = run;
   }
 }
 
@@ -306,7 +314,7 @@ hipError_t launch_partition_fill(const float* ref, int64_t N, int64_t ref_stride
 }
 
 hipError_t launch_csr_tile_offsets(const int64_t* offsets, int64_t N, int64_t* tile_off, hipStream_t s) {
-  hipLaunchKernelGGL(csr_tile_offsets_kernel, dim3(1), dim3(kPartThreads), 0, s, offsets, N, tile_off);
+  hipLaunchKernelGGL(csr_tile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, offsets, N, tile_off);
   return hipGetLastError();
 }
 

@@ -108,6 +108,28 @@ def test_csr_query_matches_dense_and_oracle(gcdf, cons, weights, precision, tol_
     assert rel.max() <= tol_j
 
 
+def test_csr_query_many_knots_matches_dense(gcdf, cons, weights):
+    """2,500 knots (more than one knot per thread of the tile-offset scan, the last
+    segments ragged), partitions of every size including empty ones: every CSR row
+    bitwise equal to the dense query's value at that (knot, point)."""
+    N, M = 2500, 1500
+    k = wl.trajectory(N, 31)
+    k[7::97, :2] += 50.0  # empty partitions spread over the scan's segments
+    p = wl.points_patches(M, 32)
+    ctx = gcdf.Context(weights.to_blob(), 256, "bf16x2")
+    kt, pt = cu(k), cu(p)
+    off, idx = ctx.partition(kt, pt, 0.6, ref_stride=9)
+    o = off.cpu().numpy()
+    print("case CSR many knots: N=%d rows=%d empty=%d" % (N, int(o[-1]), int((np.diff(o) == 0).sum())), flush=True)
+    assert (np.diff(o) == 0).sum() >= 20 and o[-1] > 0
+    c = ctx.eval_grad_csr(kt, pt, off, idx, with_grad=False)
+    d, _ = ctx.eval_grad(kt, pt)
+    torch.cuda.synchronize()
+    rows = cons.row_knots(o)
+    assert np.array_equal(c.cpu().numpy(), d.cpu().numpy()[rows, idx.cpu().numpy().astype(np.int64)])
+    ctx.close()
+
+
 def test_jacobian_pattern_bit_exact(gcdf, cons, weights):
     N = 10
     k = wl.trajectory(N, 9)
