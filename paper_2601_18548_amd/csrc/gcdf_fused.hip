@@ -846,6 +846,103 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
       }
 }
 
+// BF16 form of the same product, the operands staged in LDS: per 64-sample group
+// the workgroup's unique operand bytes (128 rows of G and 128 of H, 32 KiB) go
+// from HBM straight into LDS (global_load_lds_dwordx4, no registers), two groups
+// ahead in a ring of three, and the 4 waves read their fragments from there, so
+// each byte crosses the compute unit's L1 once instead of twice.  Group piece P
+// (1 KiB) = ((u 2 + X) 2 + kh) 2 + hf: step u of the group, operand X (G, H),
+// 8-sample block kh of the step, rows 64 hf .. 64 hf + 63 of the block's 128;
+// lane l of the copying wave fetches row 64 hf + l.
+constexpr int kWgRing = 3;                   // groups in LDS
+constexpr int kWgGroup = 64;                 // samples per group
+constexpr int kWgGroupBytes = 32 * 1024;     // 32 pieces of 1 KiB
+__global__ __launch_bounds__(256) void wgrad_gemm_lds_kernel(WgradJobs jobs, int Wd, int64_t B, int nchunks,
+                                                             int64_t chunk_len, float* __restrict__ partial) {
+  constexpr int kXcd = 8;
+  __shared__ __attribute__((aligned(16))) char ring[kWgRing * kWgGroupBytes];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tiles_n = Wd / 128, ntile = tiles_n * tiles_n;
+  const int64_t groups = (int64_t)jobs.n * nchunks;  // (GEMM, chunk) pairs
+  const int64_t b = blockIdx.x;
+  const int64_t per_xcd = (groups + kXcd - 1) / kXcd;
+  const int64_t local = b / kXcd, xcd = b % kXcd;
+  const int64_t grp = xcd * per_xcd + local / ntile;
+  if (grp >= groups) return;
+  const int tile = (int)(local % ntile);
+  const int job = (int)(grp / nchunks), chunk = (int)(grp % nchunks);
+  const int fb = (tile / tiles_n) * 128, gb = (tile % tiles_n) * 128;  // the block's rows of G and of H
+  const int64_t i0 = (int64_t)chunk * chunk_len;
+  const int64_t i1 = i0 + chunk_len < B ? i0 + chunk_len : B;
+  // rows hold zeros from B to the next multiple of 64 and chunks start at multiples of 64
+  const int ngr = (int)((i1 - i0 + kWgGroup - 1) / kWgGroup);
+  const __bf16* G = static_cast<const __bf16*>(jobs.G[job]);
+  const __bf16* H = static_cast<const __bf16*>(jobs.H[job]);
+  // this wave copies pieces 8 wave .. 8 wave + 7 of every group
+  auto issue = [&](int g) {
+    char* slot = ring + (g % kWgRing) * kWgGroupBytes;
+    const int64_t ib0 = (i0 + (int64_t)g * kWgGroup) / 8;  // first 8-sample block of the group
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int P = wave * 8 + j;
+      const int hf = P & 1, kh = (P >> 1) & 1, X = (P >> 2) & 1, u = P >> 3;
+      const __bf16* src = (X ? H : G) + ((ib0 + 2 * u + kh) * Wd + (X ? gb : fb) + 64 * hf + lane) * 8;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)(slot + P * 1024), 16, 0, 0);
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[a][c][j] = 0.f;
+  const int m = lane & 31, kh = lane >> 5;
+  const int wa = wave >> 1, wb = wave & 1;  // this wave's 64 x 64 quarter: rows 64 wa of G, 64 wb of H
+  if (ngr > 0) issue(0);
+  if (ngr > 1) issue(1);
+  for (int g = 0; g < ngr; ++g) {
+    // group g has landed once at most the next group's 8 copies are outstanding
+    if (g + 1 < ngr) __builtin_amdgcn_s_waitcnt(0x3F78);  // vmcnt(8)
+    else __builtin_amdgcn_s_waitcnt(0x3F70);              // vmcnt(0)
+    // every wave's copies of group g are in LDS, and every wave has finished
+    // reading group g - 1, whose slot the copies of group g + 2 take
+    __builtin_amdgcn_s_barrier();
+    if (g + 2 < ngr) issue(g + 2);
+    const char* slot = ring + (g % kWgRing) * kWgGroupBytes;
+    // all 16 fragments of the group first, then its 16 products
+    bf16x8 af[4][2], bf[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[u][t] = *reinterpret_cast<const bf16x8*>(slot + ((((u * 2 + 0) * 2 + kh) * 2 + wa) * 1024) + (32 * t + m) * 16);
+        bf[u][t] = *reinterpret_cast<const bf16x8*>(slot + ((((u * 2 + 1) * 2 + kh) * 2 + wb) * 1024) + (32 * t + m) * 16);
+      }
+    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb)
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[u][ta], bf[u][tb], acc[ta][tb], 0, 0, 0);
+  }
+  // C layout: lane (n = lane%32, half h) holds rows 8 (j/4) + 4 h + j%4 of column n
+  float* out = partial + ((int64_t)job * nchunks + chunk) * Wd * Wd;
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = fb + 64 * wa + 32 * ta + 8 * (j >> 2) + 4 * kh + (j & 3);
+        const int col = gb + 64 * wb + 32 * tb + m;
+        out[(int64_t)row * Wd + col] = acc[ta][tb][j];
+      }
+}
+
 // Entry (r, f) = sum over workgroups w of part[(r W + f) nparts + w]: one wave
 // per entry, lane l adding workgroups l, l + 64, ... in order, then the 64 lane
 // sums in a fixed butterfly (the result does not depend on scheduling).
@@ -920,8 +1017,7 @@ hipError_t launch_wgrad_gemm(const WgradJobs& jobs, int width, int mode, int64_t
     hipLaunchKernelGGL(wgrad_gemm_kernel<kFP32>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, chunk_len,
                        partial);
   else
-    hipLaunchKernelGGL(wgrad_gemm_kernel<kBF16>, dim3(grid), dim3(256), 0, s, jobs, width, ldb, B, nchunks, chunk_len,
-                       partial);
+    hipLaunchKernelGGL(wgrad_gemm_lds_kernel, dim3(grid), dim3(256), 0, s, jobs, width, B, nchunks, chunk_len, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)width * width;
