@@ -731,20 +731,14 @@ int64_t wgrad_partial_floats(int64_t B, int width, int num_cu) {
   return most * width * width;
 }
 
-template <int MODE>
-struct WgFrag;
-template <>
-struct WgFrag<kFP32> {
+struct WgFrag {
   f32x4 a[2], b[2];
-};
-template <>
-struct WgFrag<kBF16> {
-  bf16x8 a[2], b[2];
 };
 
 // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8); the
 // mapping below keeps the 4 output tiles of one (GEMM, chunk) on one XCD, so the
 // chunk's rows of G and H come from HBM once and are shared through that L2.
+// FP32 (the BF16 product is wgrad_gemm_lds_kernel below).
 template <int MODE>
 __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd, int64_t ldb, int64_t B, int nchunks,
                                                          int64_t chunk_len, float* __restrict__ partial) {
@@ -771,53 +765,41 @@ __global__ __launch_bounds__(256) void wgrad_gemm_kernel(WgradJobs jobs, int Wd,
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[a][c][j] = 0.f;
   const int m = lane & 31, kh = lane >> 5;
-  using E = typename std::conditional<MODE == kFP32, float, __bf16>::type;
-  constexpr int KS = MODE == kFP32 ? 8 : 16;  // samples per step
+  static_assert(MODE == kFP32, "FP32 operands");
+  using E = float;
+  constexpr int KS = 8;  // samples per step
   const E* G = static_cast<const E*>(jobs.G[job]);
   const E* H = static_cast<const E*>(jobs.H[job]);
   // The 16-byte block of S samples of feature f starts at element ((i / S) W + f) S:
   // lane (m, kh) of a step reads block i / S + kh of its row, and the 32 lanes of
   // a half read 32 consecutive features, 512 contiguous bytes.
-  constexpr int S = MODE == kFP32 ? 4 : 8;  // samples per 16-byte block (KS = 2 S)
-  constexpr int U = 4;                      // steps per prefetch group
+  constexpr int S = 4;  // samples per 16-byte block (KS = 2 S)
+  constexpr int U = 4;  // steps per prefetch group
   const E* ga[2] = {G + (int64_t)(kh * Wd + f0 + m) * S, G + (int64_t)(kh * Wd + f0 + 32 + m) * S};
   const E* hb[2] = {H + (int64_t)(kh * Wd + g0 + m) * S, H + (int64_t)(kh * Wd + g0 + 32 + m) * S};
-  auto load = [&](WgFrag<MODE>& f, int64_t i, int u) {
+  auto load = [&](WgFrag& f, int64_t i, int u) {
     const int64_t off = ((i + (int64_t)KS * u) / S) * Wd * S;  // first block of step u
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      if constexpr (MODE == kFP32) {
-        f.a[t] = *reinterpret_cast<const f32x4*>(ga[t] + off);
-        f.b[t] = *reinterpret_cast<const f32x4*>(hb[t] + off);
-      } else {
-        f.a[t] = *reinterpret_cast<const bf16x8*>(ga[t] + off);
-        f.b[t] = *reinterpret_cast<const bf16x8*>(hb[t] + off);
-      }
+      f.a[t] = *reinterpret_cast<const f32x4*>(ga[t] + off);
+      f.b[t] = *reinterpret_cast<const f32x4*>(hb[t] + off);
     }
   };
-  auto mma = [&](const WgFrag<MODE>& f) {
-    if constexpr (MODE == kFP32) {
-      // lane (m, kh) holds samples 4 kh + q of the step; MFMA q pairs samples q and 4 + q
+  auto mma = [&](const WgFrag& f) {
+    // lane (m, kh) holds samples 4 kh + q of the step; MFMA q pairs samples q and 4 + q
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int ta = 0; ta < 2; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < 2; ++tb)
-            acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[ta][q], f.b[tb][q], acc[ta][tb], 0, 0, 0);
-    } else {
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb)
-          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[ta], f.b[tb], acc[ta][tb], 0, 0, 0);
-    }
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[ta][q], f.b[tb][q], acc[ta][tb], 0, 0, 0);
   };
   // Rows hold zeros from B up to the next multiple of 64 and chunks start at
   // multiples of 64, so whole groups are read.  Double-buffered: the loads of the
   // next group are in flight while this one runs on the matrix cores.
   static_assert(U * KS <= kTileQ, "a group must not run past the zero-padded tail");
-  WgFrag<MODE> cur[U], nxt[U];
+  WgFrag cur[U], nxt[U];
   if (i0 < i1) {
 #pragma unroll
     for (int u = 0; u < U; ++u) load(cur[u], i0, u);
