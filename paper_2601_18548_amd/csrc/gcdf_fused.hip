@@ -370,9 +370,13 @@ __global__ __launch_bounds__(256) void table1_loss_kernel(const float* __restric
 __global__ void table1_loss_sum_kernel(const float* __restrict__ part, int nblocks, f32x4 lam, float* __restrict__ losses) {
   if (threadIdx.x != 0) return;
   float t[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < nblocks; ++k)
+  // the blocks in order; unrolled so that 16 blocks' loads are in flight at once
+#pragma unroll 16
+  for (int k = 0; k < nblocks; ++k) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(part + (int64_t)k * 4);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) t[c] += part[k * 4 + c];
+    for (int c = 0; c < 4; ++c) t[c] += v[c];
+  }
 #pragma unroll
   for (int c = 0; c < 4; ++c) losses[c] = t[c];
   losses[4] = lam[0] * t[0] + lam[1] * t[1] + lam[2] * t[2] + lam[3] * t[3];
