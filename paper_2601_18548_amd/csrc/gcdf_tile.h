@@ -1006,10 +1006,10 @@ __device__ __forceinline__ void input_gemm(const Lane<W, MODE>& ln, const Bases<
 
 // Last reverse layer: g1 = (W2^T g2) * SiLU'(z1) with z1 recomputed, then the
 // input-layer gradient e = W1^T g1 accumulated per lane in FP32.
-template <int W, int MODE, bool PAIRS, bool TRAIN, bool SPH>
+template <int W, int MODE, bool PAIRS, bool TRAIN, bool SPH, class F>
 __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>& ln, const Bases<W, MODE>& b,
                                           float (&epart)[2][9], const TileDump& td, const char* vb,
-                                          APre<W, MODE>& ap) {
+                                          APre<W, MODE>& ap, F&& before_copy) {
   constexpr int MT = Geo<W, MODE>::MT;
   constexpr int XF = Geo<W, MODE>::XIN_FLOATS;
   f32x16 acc[MT][2];
@@ -1122,6 +1122,7 @@ __device__ __forceinline__ void bwd_input(const DevNet& net, const Lane<W, MODE>
       });
     });
     __syncthreads();
+    before_copy();
     // g1 is needed only for db1 and dW1 = sum_i g1_i v_i^T: summed here when the
     // tile engine keeps the sums, else written out
     const DumpSums sm{td.row(0), nullptr, td.row(5), td.vt};
@@ -1217,10 +1218,14 @@ struct TileCtx {
   float* red;   // [waves][10][64]
   uint32_t* ovf;  // LDS word: a tile of this workgroup overflowed FP16 (see report_overflow)
   float b5;       // the output bias, read once (every tile's final sum adds it)
+  // BF16 training, wave 0: the next tile's inputs (knot, point, target) of this
+  // lane's query, fetched during the tile before (see process_tile)
+  float nx[13];
+  bool nx_ok;
   Lane<W, MODE> ln;
   Bases<W, MODE> b;
   __device__ __forceinline__ TileCtx(char* lds, uint32_t* ovf_word, const DevNet& net, int tid)
-      : act(lds), ovf(ovf_word), b5(*net.b5p), ln(lds, tid) {
+      : act(lds), ovf(ovf_word), b5(*net.b5p), nx_ok(false), ln(lds, tid) {
     if (tid == 0) *ovf = 0u;  // ordered before any tile's use by the tile's first barrier
     using G = Geo<W, MODE>;
     constexpr int MT = G::MT;
@@ -1305,11 +1310,34 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   const Bases<W, MODE>& b = tc.b;
   const int64_t qlimit = PAIRS ? job.npairs : (GATHER ? job.row_off[kk + 1] : job.Np);
 
+  // BF16 training: sample i = knot i, point i; the inputs of a workgroup's next tile
+  // are fetched before this tile's last copy (no vector-memory wait comes between
+  // them and the barrier that ends the tile) and read from registers by its prologue
+  constexpr bool PREFETCH = TRAIN && PAIRS && MODE == kBF16 && !SPH;
+  const bool fetched = PREFETCH && tc.nx_ok;
+  auto fetch_next = [&]() {
+    if constexpr (PREFETCH) {
+      const int64_t qn = q0 + (int64_t)gridDim.x * kTileQ;
+      tc.nx_ok = qn < qlimit && !job.csr_off && !job.kidx && !job.pidx && !job.pidx32;
+      if (tid < kTileQ && tc.nx_ok) {
+        const int64_t q = qn + tid;
+        const int64_t qc = q < qlimit ? q : qlimit - 1;
+        const float* kn = job.knots + qc * kInDim;
+#pragma unroll
+        for (int c = 0; c < kInDim; ++c) tc.nx[c] = kn[c];
+        const float* pt = job.points + qc * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tc.nx[kInDim + c] = pt[c];
+        tc.nx[12] = (!job.seed && job.target && q < qlimit) ? job.target[qc] : 0.f;
+      }
+    }
+  };
+
   // ---- prologue: base-frame points (+ per-knot arm term of the input layer) ----
   if (tid < kTileQ) {
     const int64_t q = q0 + tid;
     const int64_t qc = q < qlimit ? q : qlimit - 1;   // clamp the ragged tail (never stored)
-    int64_t ki, pi;
+    int64_t ki = 0, pi = 0;
     if constexpr (PAIRS) {
       if (job.csr_off) {
         // knot of row qc: the last i < csr_n with csr_off[i] <= qc (empty partitions skipped)
@@ -1328,16 +1356,26 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       ki = kk;
       pi = GATHER ? (int64_t)job.pgather[qc] : qc;
     }
-    const float* kn = job.knots + ki * kInDim;
-    float pxyz[4];
-    if ((PAIRS || GATHER) && (uint64_t)pi >= (uint64_t)job.Np) {
-      pxyz[0] = pxyz[1] = pxyz[2] = pxyz[3] = __builtin_nanf("");  // bad point index: NaN results
+    float kn[kInDim], pxyz[4];
+    if (fetched) {
+#pragma unroll
+      for (int c = 0; c < kInDim; ++c) kn[c] = tc.nx[c];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pxyz[c] = tc.nx[kInDim + c];
+      pxyz[3] = 0.f;
     } else {
-      const float* pt = job.points + pi * (SPH ? 4 : 3);
-      pxyz[0] = pt[0];
-      pxyz[1] = pt[1];
-      pxyz[2] = pt[2];
-      pxyz[3] = SPH ? pt[3] : 0.f;
+      const float* knp = job.knots + ki * kInDim;
+#pragma unroll
+      for (int c = 0; c < kInDim; ++c) kn[c] = knp[c];
+      if ((PAIRS || GATHER) && (uint64_t)pi >= (uint64_t)job.Np) {
+        pxyz[0] = pxyz[1] = pxyz[2] = pxyz[3] = __builtin_nanf("");  // bad point index: NaN results
+      } else {
+        const float* pt = job.points + pi * (SPH ? 4 : 3);
+        pxyz[0] = pt[0];
+        pxyz[1] = pt[1];
+        pxyz[2] = pt[2];
+        pxyz[3] = SPH ? pt[3] : 0.f;
+      }
     }
     float sn, cs;
     sincosf(kn[2], &sn, &cs);
@@ -1353,7 +1391,8 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact)
     x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : 1.f;
     // the fused loss's target, fetched with the inputs rather than after the forward
-    if constexpr (TRAIN) x[kXinTarget] = (!job.seed && job.target && q < qlimit) ? job.target[qc] : 0.f;
+    if constexpr (TRAIN)
+      x[kXinTarget] = fetched ? tc.nx[12] : (!job.seed && job.target && q < qlimit) ? job.target[qc] : 0.f;
     if constexpr (TRAIN && MODE == kBF16) {
       // the network inputs transposed and split into BF16 hi + lo, for dW1 on the
       // matrix cores (the ragged tail's inputs meet zero gradients)
@@ -1454,7 +1493,7 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
   if (want_grad) {
     bwd_hidden<W, MODE, 2, TRAIN>(net, ln, b, sp, td, ap);
     bwd_hidden<W, MODE, 1, TRAIN>(net, ln, b, sp, td, ap);
-    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td, tc.act + G::ACT_BYTES / 2, ap);
+    bwd_input<W, MODE, PAIRS, TRAIN, SPH>(net, ln, b, epart, td, tc.act + G::ACT_BYTES / 2, ap, fetch_next);
     if constexpr (rev_arith<MODE>() == kF16) {
       // a lane whose output partial sum is finite but whose input-gradient partial
       // sums are not: the FP16 reverse sweep overflowed (the forward accumulates in
