@@ -1380,7 +1380,11 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     float sn, cs;
     sincosf(kn[2], &sn, &cs);
     const float ux = pxyz[0] - kn[0], uy = pxyz[1] - kn[1];
-    float* x = xin + tid * XF;
+    // the record's address is formed here, once per tile: hoisted out of the tile
+    // loop, its pieces were kept in spill slots and reloaded one by one
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+    float* x = xin + tq * XF;
     x[0] = cs * ux + sn * uy;
     x[1] = -sn * ux + cs * uy;
     x[2] = pxyz[2];
