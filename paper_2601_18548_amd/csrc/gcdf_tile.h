@@ -1364,9 +1364,17 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
       for (int c = 0; c < 3; ++c) pxyz[c] = tc.nx[kInDim + c];
       pxyz[3] = 0.f;
     } else {
-      const float* knp = job.knots + ki * kInDim;
+      if constexpr (PAIRS) {
+        const float* knp = job.knots + ki * kInDim;
 #pragma unroll
-      for (int c = 0; c < kInDim; ++c) kn[c] = knp[c];
+        for (int c = 0; c < kInDim; ++c) kn[c] = knp[c];
+      } else {
+        // one knot per tile: scalar loads (the knots are read-only during the launch)
+        const __attribute__((address_space(4))) float* knp =
+            (const __attribute__((address_space(4))) float*)(job.knots + ki * kInDim);
+#pragma unroll
+        for (int c = 0; c < kInDim; ++c) kn[c] = knp[c];
+      }
       if ((PAIRS || GATHER) && (uint64_t)pi >= (uint64_t)job.Np) {
         pxyz[0] = pxyz[1] = pxyz[2] = pxyz[3] = __builtin_nanf("");  // bad point index: NaN results
       } else {
@@ -1438,10 +1446,17 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     }
   }
   if constexpr (!PAIRS) {
-    const float* kn = job.knots + kk * kInDim;
-    for (int r = tid; r < W; r += G::THREADS) {  // r: lane-major position
+    // the knot's arm joints, by scalar loads as above
+    const __attribute__((address_space(4))) float* ka =
+        (const __attribute__((address_space(4))) float*)(job.knots + kk * kInDim + 3);
+    float arm[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) arm[c] = ka[c];
+    int r0 = tid;  // (opaque, so the addresses below are formed here, per tile, not kept spilled)
+    asm volatile("" : "+v"(r0));
+    for (int r = r0; r < W; r += G::THREADS) {  // r: lane-major position
       const float* w = net.w1p + r * 12;
-      crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], kn + 3);
+      crow[r] = arm_term(w[3], w[4], w[5], w[6], w[7], w[8], w[9], arm);
     }
   }
   __syncthreads();
