@@ -1400,8 +1400,11 @@ __device__ __forceinline__ void process_tile(const DevNet& net, const Job& job, 
     x[4] = sn;
 #pragma unroll
     for (int c = 0; c < 6; ++c) x[5 + c] = kn[3 + c];
-    // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact)
-    x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : 1.f;
+    // reverse-sweep seed: dL/dd for training, else 1 (multiplying by 1 is exact;
+    // the constant is formed here, a copy kept from before the tile loop was spilled)
+    float one = 1.f;
+    asm volatile("" : "+v"(one));
+    x[11] = job.seed ? (q < qlimit ? job.seed[qc] : 0.f) : one;
     // the fused loss's target, fetched with the inputs rather than after the forward
     if constexpr (TRAIN)
       x[kXinTarget] = fetched ? tc.nx[12] : (!job.seed && job.target && q < qlimit) ? job.target[qc] : 0.f;
@@ -1636,6 +1639,7 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(cons
     for (int j = threadIdx.x; j < kTrainSumRows * W; j += Geo<W, MODE>::THREADS) bsum[j] = 0.f;
   }
   const int64_t nblk = PAIRS ? 0 : (job.Np + kTileQ - 1) / kTileQ;
+  int64_t kk = PAIRS ? 0 : blockIdx.x / nblk;  // dense: the knot of the current tile
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     if constexpr (PAIRS) {
       process_tile<W, MODE, true, TRAIN, false, SPH>(net, job, want_grad, 0, tile * kTileQ, tc);
@@ -1649,8 +1653,12 @@ __global__ __launch_bounds__((Geo<W, MODE>::THREADS), OCC) void fused_query(cons
       process_tile<W, MODE, false, false, true, SPH>(net, job, want_grad, lo,
                                                      job.row_off[lo] + (tile - job.tile_off[lo]) * kTileQ, tc);
     } else {
-      const int64_t kk = tile / nblk;
       process_tile<W, MODE, false, false, false, SPH>(net, job, want_grad, kk, (tile - kk * nblk) * kTileQ, tc);
+      // the next tile's knot: at most one knot further when a knot has at least as
+      // many tiles as the grid has workgroups, with no 64-bit division then
+      const int64_t next = tile + gridDim.x;
+      if (next < (kk + 2) * nblk) kk += next >= (kk + 1) * nblk ? 1 : 0;
+      else kk = next / nblk;
     }
   }
   if (bsum) {  // this workgroup's sums; summed over workgroups in order afterwards
