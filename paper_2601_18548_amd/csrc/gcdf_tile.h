@@ -695,7 +695,7 @@ struct TileDump {
   // row 15 (first entry) the fused loss sum_i (d_i - target_i)^2 / B
   float* bsum;
   __bf16* vt;  // with bsum: the tile's network inputs, transposed, BF16 hi [9][64] then lo
-  float* sp1;  // BF16: SiLU'(z1) of the input layer kept in LDS for the reverse sweep (see keep_sp1)
+  float* sp1;  // BF16: SiLU'(z1) of the input layer kept in LDS for the reverse sweep (see train_sp1)
   int width;
   __device__ __forceinline__ float* row(int r) const { return bsum ? bsum + r * width : nullptr; }
   __device__ __forceinline__ void* h(int l) const { return static_cast<char*>(H) + l * layer_elems * elem_bytes; }
@@ -949,8 +949,8 @@ __device__ __forceinline__ void bwd_hidden(const DevNet& net, const Lane<W, MODE
 }
 
 // Pure-BF16 pair-list tiles of width 256 (point obstacles; the training
-// configuration) take the input layer's
-// pre-activations from the matrix cores: z1 = b1 + W1 v over the 9 inputs, K
+// configuration) take the input layer's pre-activations from the matrix cores:
+// z1 = b1 + W1 v over the 9 inputs, K
 // padded to 16 (p' at k = 0..2, the arm joints at 3..8), as the split products
 // W1h vh + W1h vl + W1l vh accumulated in FP32 (h: the BF16 rounding, l: the BF16
 // rounding of the rest; the terms left out are below 2^-16 |W1| |v|).  The
