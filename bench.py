@@ -509,7 +509,7 @@ def main():
                     help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--no-constraints", action="store_true", help="skip the partition / CSR / projection leg")
     ap.add_argument("--no-sphere", action="store_true", help="skip the sphere-obstacle leg")
-    ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=100, help="timed training steps (0: skip)")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates: print one serving line each")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="write the HBM traffic record from the CSV output of four rocprofv3 --pmc runs "
@@ -626,10 +626,11 @@ def main():
         out["sphere"] = sphere_bench(g, torch, kernel_ms)
         print("bench: sphere %s" % json.dumps(out["sphere"]), file=sys.stderr, flush=True)
     if args.train_steps > 0:
-        out["training"] = train_bench(torch, args.train_steps, 20, cpu=not args.no_cpu_baseline)
+        # 100 untimed steps first: the step time settles only after ~20 ms of them
+        out["training"] = train_bench(torch, args.train_steps, 100, cpu=not args.no_cpu_baseline)
         print("bench: training %.3f ms/step" % out["training"]["ms_per_step"], file=sys.stderr, flush=True)
     if args.train_steps > 0:
-        out["training_table1"] = table1_bench(g, torch, max(5, args.train_steps // 4), 2)
+        out["training_table1"] = table1_bench(g, torch, max(5, args.train_steps // 20), 2)
         print("bench: Table I training %.3f ms/step" % out["training_table1"]["ms_per_step"], file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:
