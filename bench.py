@@ -44,7 +44,10 @@ DESCRIBE = {
 }
 MEETS_BAR = {"fp32": True, "bf16x2": True, "bf16x2_f16": True, "bf16": False}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_query_bf16_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2601_18548_amd", "csrc", "gcdf_tile.h")  # the query kernel's code
+# the query kernel's code: the tile engine, the structures and constants it uses, and
+# the source file that instantiates and launches it
+KERNEL_SRCS = tuple(os.path.join(ROOT, "paper_2601_18548_amd", "csrc", f)
+                    for f in ("gcdf_tile.h", "gcdf_internal.h", "gcdf_fused.hip"))
 
 
 def flops_per_pair(width: int) -> int:
@@ -56,13 +59,17 @@ def flops_per_pair(width: int) -> int:
 
 
 def kernel_source_hash(text: str | None = None) -> str:
-    """Hash of the query kernel's code with comments and blank space removed, so
-    that a comment edit does not orphan counters taken on unchanged code."""
+    """Hash of the query kernel's code (the given text, else the files of
+    KERNEL_SRCS in order) with comments and blank space removed, so that a
+    comment edit does not orphan counters taken on unchanged code."""
     import re
 
     if text is None:
-        with open(KERNEL_SRC) as f:
-            text = f.read()
+        parts = []
+        for path in KERNEL_SRCS:
+            with open(path) as f:
+                parts.append(f.read())
+        text = "\n".join(parts)
     code = re.sub(r"//[^\n]*", "", text)
     code = "\n".join(" ".join(line.split()) for line in code.splitlines() if line.strip())
     return hashlib.sha256(code.encode()).hexdigest()[:16]
